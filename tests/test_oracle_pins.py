@@ -1,0 +1,310 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term,
+a wrong sign, swapped x/y, a transposed shear, a wrong pixel rule) fails it.
+The lens equation is Eq. (1)-(3) of arXiv:1703.09707 (Sec. 1); the per-ray
+steps are those of Algorithm 1 (Sec. 2.2).
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import exact
+
+
+def _lattice(half, n):
+    dx = 2.0 * half / n
+    return (-half, -half, dx, dx, n, n, 0, 0)
+
+
+def _radii(bx, by):
+    return np.hypot(bx, by)
+
+
+# ----------------------------------------------------------------- point lens
+def _point_lens_area(b, mass=1.0):
+    # preimage of |beta| < b under beta = theta - m theta/|theta|^2 is the
+    # annulus between theta_- and theta_+ = (sqrt(b^2 + 4m) -+ b)/2
+    return math.pi * b * math.sqrt(b * b + 4.0 * mass)
+
+
+@pytest.mark.parametrize("b", [0.05, 0.2, 0.5, 1.0, 2.0])
+def test_point_lens_enclosed_count(oracle_lib, b):
+    """Single unit-mass star, no smooth matter or shear: the number of rays
+    with |beta| < b equals the preimage area pi b sqrt(b^2+4) / (dx dy)."""
+    rays = _lattice(3.0, 2000)
+    lens = (0.0, 0.0, 0.0, [0.0], [0.0], [1.0])
+    pix = (-1.0, -1.0, 0.5, 0.5, 4, 4)
+    bx, by, _ = oracle_lib.shoot(lens, rays, pix)
+    got = np.count_nonzero(_radii(bx, by) < b)
+    want = _point_lens_area(b) / (rays[2] * rays[3])
+    assert abs(got - want) / want < 5e-3, (got, want)
+
+
+def test_point_lens_magnification_profile(oracle_lib):
+    """Counts in source-plane annuli follow the point-lens magnification
+    mu(u) = (u^2 + 2) / (u sqrt(u^2 + 4)) integrated over the annulus."""
+    rays = _lattice(3.0, 2000)
+    lens = (0.0, 0.0, 0.0, [0.0], [0.0], [1.0])
+    bx, by, _ = oracle_lib.shoot(lens, rays, (-1.0, -1.0, 0.5, 0.5, 4, 4))
+    r = _radii(bx, by)
+    mu = lambda u: (u * u + 2.0) / (u * math.sqrt(u * u + 4.0))
+    edges = [0.1, 0.3, 0.6, 1.0, 1.5, 2.0]
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        got = np.count_nonzero((r >= lo) & (r < hi))
+        want = integrate.quad(lambda u: 2.0 * math.pi * u * mu(u), lo, hi)[0] / rays[2] ** 2
+        assert abs(got - want) / want < 1e-2, (lo, hi, got, want)
+
+
+def test_mass_sheet_plus_point_lens(oracle_lib):
+    """kappa_c > 0 rescales a point lens: beta/(1-kc) = theta - m' theta/|theta|^2
+    with m' = m/(1-kc), so N(|beta| < b) = pi b' sqrt(b'^2 + 4 m') / (dx dy),
+    b' = b / (1 - kc)."""
+    kc, m = 0.3, 0.7
+    rays = _lattice(3.0, 2000)
+    lens = (kc, 0.0, 0.0, [0.0], [0.0], [m])
+    bx, by, _ = oracle_lib.shoot(lens, rays, (-1.0, -1.0, 0.5, 0.5, 4, 4))
+    r = _radii(bx, by)
+    for b in (0.1, 0.5, 1.0):
+        bp = b / (1.0 - kc)
+        want = _point_lens_area(bp, m / (1.0 - kc)) / rays[2] ** 2
+        got = np.count_nonzero(r < b)
+        assert abs(got - want) / want < 5e-3, (b, got, want)
+
+
+def test_off_centre_star_translation(oracle_lib):
+    """Moving the star and the lattice together moves beta by the same
+    amount when there is no smooth matter or shear."""
+    rays = (-1.0, -1.0, 1 / 64, 1 / 64, 128, 128, 0, 0)
+    pix = (-1.0, -1.0, 1 / 8, 1 / 8, 16, 16)
+    bx, by, _ = oracle_lib.shoot((0.0, 0.0, 0.0, [0.25], [-0.375], [0.5]), rays, pix)
+    rays2 = (1.0, -3.0, 1 / 64, 1 / 64, 128, 128, 0, 0)
+    bx2, by2, _ = oracle_lib.shoot((0.0, 0.0, 0.0, [2.25], [-2.375], [0.5]), rays2, pix)
+    np.testing.assert_allclose(bx2 - 2.0, bx, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(by2 + 2.0, by, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------- sheets
+@pytest.mark.parametrize("kc,g1,g2", [(0.25, 0.125, 0.0), (0.25, 0.125, 0.0625),
+                                      (0.5, -0.25, 0.1875), (0.0, 0.0, 0.0)])
+def test_dyadic_sheet_is_exact(oracle_lib, kc, g1, g2):
+    """No stars and dyadic kappa_c, gamma, lattice and window: every beta and
+    pixel coordinate is exact in FP64, so the oracle equals exact rational
+    arithmetic ray by ray, pixel-edge ties included (a tie goes up)."""
+    # origin shifted by half a cell so that theta = -2 + i/32, -1.5 + j/64
+    rays = (-2.0 - 1 / 64, -1.5 - 1 / 128, 1 / 32, 1 / 64, 128, 192, 0, 0)
+    pix = (-1.5, -1.25, 1 / 16, 1 / 8, 48, 20)
+    lens = (kc, g1, g2, [], [], [])
+    bx, by, b = oracle_lib.shoot(lens, rays, pix)
+    ex = exact.exact_shoot(lens, rays, pix)
+    ties = 0
+    for r, (beta, p, edge) in enumerate(ex):
+        j, i = divmod(r, rays[4])
+        assert Fraction(bx[j, i]) == beta[0] and Fraction(by[j, i]) == beta[1]
+        assert b[j, i] == p
+        ties += edge == 0
+    assert ties > 0  # the lattice puts some rays exactly on pixel edges
+
+
+def test_sheet_area_law(oracle_lib):
+    """A smooth sheet maps a region S onto |S|/|det A| of lens-plane area:
+    counts in the window equal window area / (|det A| dx dy) up to the
+    boundary rays."""
+    kc, g1, g2 = 0.2, 0.3, -0.15
+    det = (1 - kc) ** 2 - g1 ** 2 - g2 ** 2
+    rays = _lattice(6.0, 1200)
+    pix = (-2.0, -2.0, 0.125, 0.125, 32, 32)
+    counts, n = oracle_lib.map_counts((kc, g1, g2, [], [], []), rays, pix)
+    want = 16.0 / (abs(det) * rays[2] * rays[3])
+    assert abs(n - want) / want < 3e-3, (n, want)
+    assert counts.sum() == n
+
+
+def test_pixel_edges_and_window(oracle_lib):
+    """Identity lens: rays placed exactly on pixel edges go to the upper
+    pixel; the window is half open [X0, X0 + NX Px)."""
+    P, NX = 0.25, 8
+    X0, Y0 = -1.0, 0.5
+    dx = P / 4
+    # theta_i = X0 + (i - 1) dx for i = 0 .. 4 NX + 1 (ray 0 left of the window)
+    rays = (X0 - 1.5 * dx, Y0 + 0.0, dx, P, 4 * NX + 2, 1, 0, 0)
+    pix = (X0, Y0, P, P, NX, 1)
+    _, _, b = oracle_lib.shoot((0.0, 0.0, 0.0, [], [], []), rays, pix)
+    b = b[0]
+    assert b[0] == -1              # theta = X0 - dx: outside
+    assert b[1] == 0               # theta = X0 exactly: first pixel
+    for i in range(1, 4 * NX + 1):
+        assert b[i] == (i - 1) // 4
+    assert b[4 * NX + 1] == -1     # theta = X0 + NX P exactly: outside
+
+
+def test_ray_on_star_is_dropped(oracle_lib):
+    """A ray exactly on a star has no finite source angle and is not binned."""
+    rays = (-1.0, -1.0, 0.25, 0.25, 8, 8, 0, 0)   # theta = -0.875 + 0.25 k
+    star = (-0.375, 0.125)                         # lattice point (i, j) = (2, 4)
+    lens = (0.1, 0.05, 0.0, [star[0]], [star[1]], [0.3])
+    pix = (-4.0, -4.0, 0.5, 0.5, 16, 16)
+    bx, by, b = oracle_lib.shoot(lens, rays, pix)
+    assert not np.isfinite(bx[4, 2]) or not np.isfinite(by[4, 2])
+    assert b[4, 2] == -1
+    counts, n = oracle_lib.map_counts(lens, rays, pix)
+    assert n == np.count_nonzero(b >= 0) == 63
+
+
+# ----------------------------------------------------------------- exact brute force
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_exact_rational_brute_force(oracle_lib, seed):
+    """Random stars, smooth matter and shear on a tiny dyadic lattice:
+    the FP64 oracle's beta is within rounding of the exact rational beta and
+    every bin matches except rays within 1e-9 of a pixel edge."""
+    rng = np.random.default_rng(seed)
+    n_st = 4
+    xs = rng.uniform(-2, 2, n_st)
+    ys = rng.uniform(-2, 2, n_st)
+    ms = rng.uniform(0.1, 1.0, n_st)
+    kc, g1, g2 = rng.uniform(0, 0.4), rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3)
+    lens = (kc, g1, g2, xs, ys, ms)
+    rays = (-2.0, -2.0, 0.25, 0.25, 16, 16, 0, 0)
+    pix = (-3.0, -3.0, 0.1875, 0.1875, 32, 32)
+    bx, by, b = oracle_lib.shoot(lens, rays, pix)
+    ex = exact.exact_shoot(lens, rays, pix)
+    tx, ty = oracle_lib.image_angles(rays)
+    near = 0
+    for r, (beta, p, edge) in enumerate(ex):
+        j, i = divmod(r, 16)
+        s = oracle_lib.error_scale(lens, tx[i], ty[j])[0]
+        assert abs(bx[j, i] - float(beta[0])) <= 1e-13 * s
+        assert abs(by[j, i] - float(beta[1])) <= 1e-13 * s
+        if edge < 1e-9:
+            near += 1
+            continue
+        assert b[j, i] == p, (i, j)
+    assert near == 0
+
+
+# ----------------------------------------------------------------- invariants
+def _random_lens(rng, n=40, radius=3.0):
+    r = radius * np.sqrt(rng.random(n))
+    phi = 2 * np.pi * rng.random(n)
+    return (0.12, 0.21, -0.07, r * np.cos(phi), r * np.sin(phi), rng.uniform(0.1, 1.0, n))
+
+
+def test_map_is_histogram_of_bins(oracle_lib):
+    """Conservation: the map equals the histogram of per-ray bins, and every
+    ray is binned, outside or dropped."""
+    rng = np.random.default_rng(7)
+    lens = _random_lens(rng)
+    rays = (-4.0, -3.0, 8 / 200, 6 / 150, 200, 150, 0, 0)
+    pix = (-2.0, -2.0, 4 / 64, 4 / 64, 64, 64)
+    _, _, b = oracle_lib.shoot(lens, rays, pix)
+    counts, n = oracle_lib.map_counts(lens, rays, pix)
+    hist = np.bincount(b[b >= 0], minlength=64 * 64).reshape(64, 64)
+    np.testing.assert_array_equal(counts, hist)
+    assert n == counts.sum() == np.count_nonzero(b >= 0)
+    assert n + np.count_nonzero(b < 0) == 200 * 150
+
+
+def test_mirror_symmetry(oracle_lib):
+    """Mirroring the stars x -> -x and gamma2 -> -gamma2 on a lattice and
+    window symmetric about x = 0 mirrors every source angle exactly
+    (IEEE rounding is sign symmetric)."""
+    rng = np.random.default_rng(11)
+    kc, g1, g2, xs, ys, ms = _random_lens(rng)
+    nx = 96
+    rays = (-nx / 64, -1.0, 1 / 32, 1 / 48, nx, 96, 0, 0)
+    pix = (-2.0, -2.0, 0.125, 0.125, 32, 32)
+    bx, by, b = oracle_lib.shoot((kc, g1, g2, xs, ys, ms), rays, pix)
+    mx, my, mb = oracle_lib.shoot((kc, g1, -g2, -xs, ys, ms), rays, pix)
+    np.testing.assert_array_equal(mx[:, ::-1], -bx)
+    np.testing.assert_array_equal(my[:, ::-1], by)
+    c1, _ = oracle_lib.map_counts((kc, g1, g2, xs, ys, ms), rays, pix)
+    c2, _ = oracle_lib.map_counts((kc, g1, -g2, -xs, ys, ms), rays, pix)
+    np.testing.assert_array_equal(c2[:, ::-1], c1)
+
+
+def test_band_additivity(oracle_lib):
+    """A block of the lattice (offset i0, j0) gives bit-identical rays, so
+    the full map equals the sum of the maps of any split into bands."""
+    rng = np.random.default_rng(5)
+    lens = _random_lens(rng)
+    full = (-4.0, -3.0, 0.037, 0.029, 150, 120, 0, 0)
+    pix = (-2.0, -2.0, 4 / 64, 4 / 64, 64, 64)
+    fx, fy, fb = oracle_lib.shoot(lens, full, pix)
+    total, _ = oracle_lib.map_counts(lens, full, pix)
+    acc = np.zeros_like(total)
+    for j0, nyb in ((0, 50), (50, 1), (51, 69)):
+        for i0, nxb in ((0, 77), (77, 73)):
+            blk = (-4.0, -3.0, 0.037, 0.029, nxb, nyb, i0, j0)
+            bx, by, b = oracle_lib.shoot(lens, blk, pix)
+            np.testing.assert_array_equal(bx, fx[j0:j0 + nyb, i0:i0 + nxb])
+            np.testing.assert_array_equal(by, fy[j0:j0 + nyb, i0:i0 + nxb])
+            oracle_lib.map_counts(lens, blk, pix, acc)
+    np.testing.assert_array_equal(acc, total)
+
+
+def test_star_sum_is_linear(oracle_lib):
+    """alpha is additive over stars: beta(A u B) = beta(A) + beta(B) - (I - K) theta
+    to rounding; permuting the stars changes beta only by rounding."""
+    rng = np.random.default_rng(3)
+    kc, g1, g2, xs, ys, ms = _random_lens(rng, n=30)
+    rays = (-3.0, -3.0, 6 / 40, 6 / 40, 40, 40, 0, 0)
+    pix = (-1.0, -1.0, 0.5, 0.5, 4, 4)
+    ab = oracle_lib.shoot((kc, g1, g2, xs, ys, ms), rays, pix)
+    a = oracle_lib.shoot((kc, g1, g2, xs[:13], ys[:13], ms[:13]), rays, pix)
+    bb = oracle_lib.shoot((kc, g1, g2, xs[13:], ys[13:], ms[13:]), rays, pix)
+    sheet = oracle_lib.shoot((kc, g1, g2, [], [], []), rays, pix)
+    tx, ty = oracle_lib.image_angles(rays)
+    s = oracle_lib.error_scale((kc, g1, g2, xs, ys, ms), np.tile(tx, 40), np.repeat(ty, 40)).reshape(40, 40)
+    for c in (0, 1):
+        np.testing.assert_array_less(np.abs(ab[c] - (a[c] + bb[c] - sheet[c])), 1e-13 * s)
+    perm = rng.permutation(len(xs))
+    p = oracle_lib.shoot((kc, g1, g2, xs[perm], ys[perm], ms[perm]), rays, pix)
+    for c in (0, 1):
+        np.testing.assert_array_less(np.abs(ab[c] - p[c]), 1e-13 * s)
+
+
+def test_mean_magnification_of_star_field(oracle_lib):
+    """Many light stars approach a smooth sheet: the mean magnification of
+    the window tends to 1/|(1-k)^2 - gamma^2| with k = kappa_c + kappa_star.
+    This pins the normalisation of the star term of Eq. (1) (a star of mass m
+    has Einstein radius sqrt(m), so a disk of radius R holding masses m_k has
+    kappa_star = sum m_k / R^2) and the sign of every term."""
+    from paper_1703_09707_amd import workloads as W
+    rng = np.random.Generator(np.random.PCG64(1))
+    ks, kc, g1, g2 = 0.3, 0.15, 0.2, 0.0
+    hx, hy = W.preimage_half_widths(kc + ks, g1, g2, 1.0, 1.0, margin=1.5)
+    m = W.equal_masses(10000, 0.003)
+    x, y, radius = W.star_field(m, ks, rng)
+    assert radius > 2 * math.hypot(hx, hy)
+    rays = (-hx, -hy, 2 * hx / 300, 2 * hy / 300, 300, 300, 0, 0)
+    pix = (-1.0, -1.0, 2 / 16, 2 / 16, 16, 16)
+    counts, n = oracle_lib.map_counts((kc, g1, g2, x, y, m), rays, pix)
+    mu = n * rays[2] * rays[3] / 4.0
+    want = W.mean_magnification(kc + ks, g1, g2)
+    assert abs(mu / want - 1) < 0.05, (mu, want)
+
+
+# ----------------------------------------------------------------- golden fixture
+def test_golden_exact_tiny(oracle_lib):
+    """The FP64 oracle reproduces the stored exact-rational case bin for bin
+    (rays within 1e-9 of a pixel edge excepted), including the dropped ray
+    that sits exactly on a star."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "exact_tiny.json")))
+    L, R, P = g["lens"], g["rays"], g["pix"]
+    lens = (L["kappa_c"], L["gamma1"], L["gamma2"], L["x"], L["y"], L["m"])
+    rays = tuple(R[k] for k in ("x0", "y0", "dx", "dy", "nx", "ny", "i0", "j0"))
+    pix = tuple(P[k] for k in ("X0", "Y0", "Px", "Py", "NX", "NY"))
+    _, _, b = oracle_lib.shoot(lens, rays, pix)
+    b = b.ravel()
+    want = np.array(g["bins"])
+    near = np.array(g["edge_distance"]) < 1e-9
+    assert np.count_nonzero(want == -1) > 0
+    np.testing.assert_array_equal(b[~near], want[~near])
+    counts, n = oracle_lib.map_counts(lens, rays, pix)
+    if not near.any():
+        np.testing.assert_array_equal(counts.ravel(), np.array(g["counts"]))
