@@ -1,0 +1,152 @@
+"""Benchmark: backward ray shooting (arXiv:1703.09707, Algorithm 1) on one MI355X.
+
+A step is one pass of Algorithm 1 over the whole workload: every ray of the
+8192 x 8192 lattice through all 16384 stars, binned into the 1024 x 1024 map
+(raysh_map, FP64).  Inputs (stars, map) are resident in device memory before
+the timed region.  The FP32-bulk form is timed the same way and reported
+beside it.
+
+Metric: ray-star interactions per second (N_rays * N_stars / time), with
+rays/s alongside.  The roofline object prices the FP64 kernel's algorithmic
+FLOPs (10 per interaction: 2 subtractions, 2 multiplies and 1 add for r^2,
+1 division, 2 multiply-adds for the accumulation) against the FP64 vector
+peak; the kernel's own time comes from HIP events recorded on the stream the
+kernel runs on.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_INTERACTION = 10
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk timing")
+    ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
+    ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
+    ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
+    return ap.parse_args()
+
+
+def time_steps(torch, ctx, w, precision, counts, steps, warmup):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.map(w.rays, w.pix, precision, counts=counts)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        ctx.map(w.rays, w.pix, precision, counts=counts)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return wall, kernel_ms
+
+
+def cpu_baseline(w, side):
+    """The oracle, as it stands, on the central side x side rays."""
+    from oracle import shooter as ora
+    blk = w.rays.block((w.rays.nx - side) // 2, (w.rays.ny - side) // 2, side, side)
+    t0 = time.perf_counter()
+    ora.map_counts(w.lens.as_tuple(), blk.as_tuple(), w.pix.as_tuple())
+    dt = time.perf_counter() - t0
+    inter = blk.n_rays * w.lens.n_stars
+    return {"value": inter / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"central {side}x{side} rays of the 8192^2 lattice x {w.lens.n_stars} stars "
+                      f"({inter:.3e} interactions, {dt:.1f} s, single thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form "
+              "(ray-band sharding plus an int32 map reduce) is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1703_09707_amd import raysh
+    from paper_1703_09707_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    w = W.plain_fp64_large()
+    inter = w.interactions
+    ctx = raysh.Context(w.lens, device=0)
+    if args.tile:
+        cx, cy, sh = (int(v) for v in args.tile.split(","))
+        ctx.set_tile("fp64", cx, cy, share=sh)
+    if args.tile32:
+        cx, cy, st = (int(v) for v in args.tile32.split(","))
+        ctx.set_tile("fp32_bulk", cx, cy, star_tile=st)
+    counts = torch.zeros((w.pix.NY, w.pix.NX), dtype=torch.int32, device="cuda")
+
+    print(f"# fp64: {args.steps} steps after {args.warmup} warmup", file=sys.stderr, flush=True)
+    wall, kms = time_steps(torch, ctx, w, "fp64", counts, args.steps, args.warmup)
+    ms_step = 1e3 * wall / args.steps
+    k_avg = sum(kms) / len(kms)
+    achieved = FLOP_PER_INTERACTION * inter / (k_avg * 1e-3) / 1e12
+
+    out = {
+        "metric": "ray-star interactions/s at 1 GPU (FP64 backward ray shooting, Algorithm 1)",
+        "value": inter / (wall / args.steps),
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded star field, Salpeter masses)",
+        "config": {"workload": "plain-fp64-large", "n_stars": w.lens.n_stars,
+                   "rays": [w.rays.nx, w.rays.ny], "map": [w.pix.NX, w.pix.NY],
+                   "kappa_star": w.lens.kappa_star, "kappa_c": w.lens.kappa_c,
+                   "gamma": [w.lens.gamma1, w.lens.gamma2],
+                   "tile_fp64": list(ctx.get_tile("fp64"))},
+        "rays_per_s": w.rays.n_rays / (wall / args.steps),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "shoot_fp64_kernel",
+                     "kernel_ms": k_avg,
+                     "flop_per_launch": FLOP_PER_INTERACTION * inter},
+    }
+    if not args.no_fp32:
+        print("# fp32_bulk", file=sys.stderr, flush=True)
+        c32 = torch.zeros_like(counts)
+        wall32, kms32 = time_steps(torch, ctx, w, "fp32_bulk", c32, args.steps, args.warmup)
+        m64 = ctx.map(w.rays, w.pix, "fp64")
+        m32 = ctx.map(w.rays, w.pix, "fp32_bulk")
+        l1 = int((m64.long() - m32.long()).abs().sum())
+        dn = abs(int(m64.long().sum()) - int(m32.long().sum()))
+        out["fp32_bulk"] = {
+            "value": inter / (wall32 / args.steps), "unit": "interactions/s",
+            "ms_per_step": 1e3 * wall32 / args.steps, "kernel_ms": sum(kms32) / len(kms32),
+            "speedup_vs_fp64": wall / wall32,
+            "misbinned_fraction_lower_bound": 0.5 * (l1 + dn) / w.rays.n_rays,
+            "tile": list(ctx.get_tile("fp32_bulk"))}
+    ctx.close()
+    if not args.no_cpu:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * raysh: backward ray shooting through a random star field on AMD MI355X.
+ *
+ * The method is that of Chen, Kantowski, Dai, Baron & Van der Mark (2017),
+ * "Accelerating gravitational microlensing simulations using the Xeon Phi
+ * coprocessor" (arXiv:1703.09707):
+ *   - the lens equation, Sec. 1, Eq. (1)-(3): a ray at image angle theta
+ *     reaches the source plane at beta = theta - alpha with
+ *       alpha = K theta + sum_k m_k (theta - theta_k) / |theta - theta_k|^2,
+ *       K = [[kappa_c + gamma1, gamma2], [gamma2, kappa_c - gamma1]];
+ *     angles are in units of the Einstein angle of the mass unit and m_k in
+ *     that mass unit (Eq. (4) and the text after it);
+ *   - Algorithm 1 (Sec. 2.2): for every ray of a regular lattice, evaluate
+ *     theta, add the macro term and every star's term in index order, form
+ *     beta, convert it to a source-plane pixel and, if it lies inside the
+ *     source window, add one to that pixel's count (the magnification map).
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - Ray (i, j) of a call has global lattice indices (i0 + i, j0 + j) and
+ *     image angle theta = (x0 + ((double)(i0+i) + 0.5) * dx,
+ *                          y0 + ((double)(j0+j) + 0.5) * dy),
+ *     each operation rounded separately, so a block of a lattice reproduces
+ *     the rays of the whole lattice bit for bit.
+ *   - Pixel (is, js) covers [x0 + is*px, x0 + (is+1)*px) x [y0 + js*py, ...).
+ *     The pixel coordinate is (beta - x0) / px with IEEE division, tested
+ *     against the window in FP64 before conversion; maps are row-major int32
+ *     [ny][nx] with element js*nx + is (the paper's mag[j_s, i_s]).
+ *   - A ray whose beta is not finite (it sits exactly on a star) is dropped.
+ *
+ * Memory: star arrays passed to raysh_init are host memory and are copied;
+ * every other pointer (maps, per-ray outputs) is caller-owned DEVICE memory
+ * on the context's device.  The library never allocates caller outputs.
+ * Work is enqueued on the context's HIP stream and is asynchronous unless a
+ * function says otherwise.
+ *
+ * Errors: every function returns RAYSH_OK (0) or a RAYSH_E* code, and
+ * raysh_last_error() gives a message for the calling thread's last error.
+ * Arguments are validated before anything is enqueued: on error nothing is
+ * written.  A context is used by one host thread at a time.
+ */
+#ifndef RAYSH_H
+#define RAYSH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RAYSH_OK = 0,
+    RAYSH_EINVAL = 1,    /* bad argument: NULL, non-finite, non-positive size, unknown precision */
+    RAYSH_EOVERFLOW = 2, /* a count or index would not fit the library's integer types */
+    RAYSH_ENOMEM = 3,    /* device allocation failed */
+    RAYSH_EDEVICE = 4    /* HIP runtime error (including an earlier asynchronous one) */
+};
+
+/* Arithmetic of the star sum. */
+enum {
+    RAYSH_FP64 = 0,      /* every step in FP64 */
+    RAYSH_FP32_BULK = 1  /* star terms in FP32 on tile-relative coordinates,
+                            flushed into FP64 sums; theta, the macro term and
+                            the beta -> pixel step stay FP64 */
+};
+
+/* The lens of Eq. (1): smooth convergence, external shear and the stars.
+ * x, y, m are HOST arrays of n_stars FP64 values (positions in Einstein
+ * angles, masses in the mass unit); they may be NULL when n_stars == 0. */
+typedef struct raysh_lens {
+    double kappa_c;
+    double gamma1;
+    double gamma2;
+    int64_t n_stars;
+    const double *x;
+    const double *y;
+    const double *m;
+} raysh_lens;
+
+/* A block of the image-plane ray lattice (see the theta convention above). */
+typedef struct raysh_rays {
+    double x0, y0;   /* lattice origin (corner of cell (0, 0)) */
+    double dx, dy;   /* lattice spacing, > 0 */
+    int64_t nx, ny;  /* rays in this block, >= 0 */
+    int64_t i0, j0;  /* global index of the block's first ray, >= 0 */
+} raysh_rays;
+
+/* The source window and its pixels (see the pixel convention above). */
+typedef struct raysh_pixels {
+    double x0, y0;   /* lower-left corner of the window */
+    double px, py;   /* pixel size, > 0 */
+    int32_t nx, ny;  /* pixels per row and rows, > 0 */
+} raysh_pixels;
+
+typedef struct raysh_ctx raysh_ctx;
+
+/*
+ * raysh_init: create a context on HIP device `device` whose work goes to
+ * HIP stream `hip_stream` (NULL = the null stream), validate the lens and
+ * copy the star field to the device (Sec. 2.2: the star field is generated
+ * on the host and copied to the accelerator once).
+ *   EINVAL: out == NULL; kappa_c or gamma not finite; n_stars < 0; a star
+ *           array NULL with n_stars > 0; a position not finite; a mass
+ *           negative or not finite.  EOVERFLOW: n_stars > 2^31 - 1.
+ *   ENOMEM / EDEVICE from the runtime.  On error *out is left unchanged.
+ * The caller may free its star arrays as soon as the call returns.
+ */
+int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_stream);
+
+/* Redirect the context's work to another HIP stream of the same device. */
+int raysh_set_stream(raysh_ctx *ctx, void *hip_stream);
+
+/* Number of stars held by the context (0 for a NULL context). */
+int64_t raysh_n_stars(const raysh_ctx *ctx);
+
+/*
+ * Launch shape of the context's kernels for one precision (the autotuner's
+ * knob; results do not depend on it for RAYSH_FP64).  Each lane of a
+ * 256-lane workgroup owns cx x cy rays of a (16 cx) x (16 cy) ray tile;
+ * `share` stars share one reciprocal in the FP64 star sum; `star_tile`
+ * stars are staged in LDS per pass in the FP32-bulk sum (the FP32 partial
+ * sums are flushed into FP64 after each pass).  Fields that do not apply to
+ * the precision are ignored by raysh_get_tile callers and must be 0 in
+ * raysh_set_tile.  EINVAL if the shape is not compiled into the library.
+ */
+int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int star_tile);
+int raysh_get_tile(const raysh_ctx *ctx, int precision, int *cx, int *cy, int *share,
+                   int *star_tile);
+
+/*
+ * raysh_autotune: time every launch shape compiled for `precision` on a
+ * central sample of the ray block (about 2e10 / n_stars rays, at least
+ * 256 x 256, at most the block) mapped into a scratch map, keep the fastest
+ * in the context (as raysh_set_tile would) and return it through the
+ * optional out-pointers.  cache_path (when NULL, the environment variable
+ * RAYSH_AUTOTUNE_CACHE; no cache if both are unset) names a text file of
+ * earlier choices keyed by GPU architecture, CU count, precision and
+ * log2(n_stars): a hit skips the timing, a miss appends a line.
+ * Synchronous.  Errors as raysh_map; ENOMEM if the scratch map cannot be
+ * allocated.
+ */
+int raysh_autotune(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix, int precision,
+                   const char *cache_path, int *cx, int *cy, int *share, int *star_tile);
+
+/*
+ * raysh_shoot: per-ray results of Eq. (1) for one block of rays.
+ *   beta_x, beta_y: device FP64 arrays of nx*ny, element j*nx + i
+ *                   (may be NULL); written with beta of ray (i, j).
+ *   bin:            device int32 array of nx*ny (may be NULL, then pix may
+ *                   be NULL); written with the linear pixel index
+ *                   js*pix->nx + is, or -1 when the ray is dropped or
+ *                   outside the window.
+ * EINVAL on bad rays/pixels/precision, on a NULL ctx, or when an output
+ * pointer is not device memory large enough for nx*ny elements;
+ * EOVERFLOW when nx*ny > 2^31 - 1 or i0 + nx, j0 + ny > 2^53.
+ * An empty block (nx or ny == 0) is a no-op.
+ */
+int raysh_shoot(raysh_ctx *ctx, const raysh_rays *rays, int precision,
+                double *beta_x, double *beta_y, const raysh_pixels *pix, int32_t *bin);
+
+/*
+ * raysh_map: Algorithm 1 for one block of rays: ADDS one to counts[js*nx + is]
+ * for every ray that lands in the window (the map is accumulated, never
+ * cleared, so maps of disjoint blocks of one lattice sum to the map of the
+ * whole lattice).  counts: device int32 [pix->ny][pix->nx].
+ * n_binned (optional, HOST pointer): if not NULL, the call waits for the
+ * stream and stores the number of rays this call binned.
+ * Errors as raysh_shoot; EINVAL also when counts is NULL or not device
+ * memory of nx*ny int32.  Counts wrap silently only if one pixel receives
+ * more than 2^31 - 1 rays over several calls (one call cannot: its ray count
+ * is below 2^31).
+ */
+int raysh_map(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix,
+              int precision, int32_t *counts, uint64_t *n_binned);
+
+/*
+ * raysh_map_batch: raysh_map for n_sets independent lenses in one launch
+ * (Sec. 2.2 mentions grids of independent simulations over lens parameters).
+ * sets[s] is a context (all on one device; the stream of sets[0] is used),
+ * rays[s], pix[s] its lattice block and window, counts[s] its device map.
+ * Work items (set, ray tile) are ordered longest first and drained by a
+ * persistent grid from a device work queue; the launch is captured once into
+ * a HIP graph per (sets, shapes) and replayed when the same batch is run again.
+ * Maps are accumulated, as in raysh_map.  Errors: as raysh_map for every set,
+ * EINVAL if n_sets < 1 or the contexts are on different devices.
+ */
+int raysh_map_batch(raysh_ctx *const *sets, int n_sets, const raysh_rays *rays,
+                    const raysh_pixels *pix, int precision, int32_t *const *counts);
+
+/* Wait for all work enqueued by the context. */
+int raysh_sync(raysh_ctx *ctx);
+
+/* Release a context (waits for its work first).  NULL is a no-op. */
+int raysh_free(raysh_ctx *ctx);
+
+/* Message for the calling thread's last error ("" if none). */
+const char *raysh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAYSH_H */

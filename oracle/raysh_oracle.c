@@ -171,3 +171,18 @@ double ora_error_scale(double kappa_c, double gamma1, double gamma2,
     }
     return s;
 }
+
+/* error scale of every ray of a lattice block, j-major */
+void ora_error_scale_block(double kappa_c, double gamma1, double gamma2,
+                           int64_t n_stars, const double *xs, const double *ys, const double *ms,
+                           double x0, double y0, double dx, double dy,
+                           int64_t nx, int64_t ny, int64_t i0, int64_t j0, double *scale)
+{
+    for (int64_t j = 0; j < ny; ++j) {
+        double ty = image_angle(y0, j0 + j, dy);
+        for (int64_t i = 0; i < nx; ++i) {
+            double tx = image_angle(x0, i0 + i, dx);
+            scale[j * nx + i] = ora_error_scale(kappa_c, gamma1, gamma2, n_stars, xs, ys, ms, tx, ty);
+        }
+    }
+}

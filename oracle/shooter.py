@@ -31,6 +31,8 @@ def load_library(path):
     lib.ora_shoot_list.restype = None
     lib.ora_error_scale.argtypes = [_D, _D, _D, _I64, _P, _P, _P, _D, _D]
     lib.ora_error_scale.restype = _D
+    lib.ora_error_scale_block.argtypes = head + [_I64, _I64, _I64, _I64, _P]
+    lib.ora_error_scale_block.restype = None
     return lib
 
 
@@ -119,6 +121,17 @@ def error_scale(lens, tx, ty, lib=None):
     ty = np.atleast_1d(np.asarray(ty, np.float64))
     return np.array([lib.ora_error_scale(kc, g1, g2, len(x), _ptr(x), _ptr(y), _ptr(m),
                                          float(a), float(b)) for a, b in zip(tx, ty)])
+
+
+def error_scale_block(lens, rays, lib=None):
+    """Error scale S of every ray of a lattice block, shape (ny, nx)."""
+    kc, g1, g2, x, y, m = lens
+    x, y, m = _stars(x, y, m)
+    x0, y0, dx, dy, nx, ny, i0, j0 = rays
+    out = np.empty((ny, nx), np.float64)
+    (lib or _load()).ora_error_scale_block(kc, g1, g2, len(x), _ptr(x), _ptr(y), _ptr(m),
+                                           x0, y0, dx, dy, nx, ny, i0, j0, _ptr(out))
+    return out
 
 
 def image_angles(rays):

@@ -1,0 +1,326 @@
+// Host side of the raysh C ABI: argument validation, contexts, star upload
+// and kernel dispatch.  The operation itself is Eq. (1)-(3) and Algorithm 1
+// of arXiv:1703.09707 (see include/raysh.h for the conventions).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "raysh_ctx.h"
+
+using raysh::ShootParams;
+using raysh::Star;
+using raysh::TileShape;
+
+
+namespace {
+
+thread_local char g_err[512] = "";
+constexpr int64_t kMaxRays = std::numeric_limits<int32_t>::max();
+constexpr int64_t kMaxIndex = int64_t(1) << 53;
+
+hipError_t launch(const raysh_ctx *c, const ShootParams &p, int precision) {
+    if (precision == RAYSH_FP64) return raysh::launch_shoot_fp64(p, c->shape[0], c->stream);
+    return raysh::launch_shoot_fp32(p, c->shape[1], c->stream);
+}
+
+}  // namespace
+
+int set_error(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int set_ok() {
+    g_err[0] = '\0';
+    return RAYSH_OK;
+}
+
+int hip_error(hipError_t e, const char *what) {
+    return set_error(RAYSH_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int validate_rays(const raysh_rays *r) {
+    if (!r) return set_error(RAYSH_EINVAL, "rays is NULL");
+    if (!std::isfinite(r->x0) || !std::isfinite(r->y0))
+        return set_error(RAYSH_EINVAL, "ray lattice origin is not finite");
+    if (!(std::isfinite(r->dx) && r->dx > 0) || !(std::isfinite(r->dy) && r->dy > 0))
+        return set_error(RAYSH_EINVAL, "ray spacing must be finite and > 0");
+    if (r->nx < 0 || r->ny < 0) return set_error(RAYSH_EINVAL, "ray counts must be >= 0");
+    if (r->i0 < 0 || r->j0 < 0) return set_error(RAYSH_EINVAL, "ray block offsets must be >= 0");
+    if (r->i0 > kMaxIndex - r->nx || r->j0 > kMaxIndex - r->ny)
+        return set_error(RAYSH_EOVERFLOW, "ray lattice index beyond 2^53");
+    if (r->nx > 0 && r->ny > kMaxRays / r->nx)
+        return set_error(RAYSH_EOVERFLOW, "more than 2^31-1 rays in one call");
+    const double ex = r->x0 + ((double)(r->i0 + r->nx) + 0.5) * r->dx;
+    const double ey = r->y0 + ((double)(r->j0 + r->ny) + 0.5) * r->dy;
+    if (!std::isfinite(ex) || !std::isfinite(ey))
+        return set_error(RAYSH_EINVAL, "image angles of the lattice are not finite");
+    return RAYSH_OK;
+}
+
+int validate_pixels(const raysh_pixels *p) {
+    if (!p) return set_error(RAYSH_EINVAL, "pixels is NULL");
+    if (!std::isfinite(p->x0) || !std::isfinite(p->y0))
+        return set_error(RAYSH_EINVAL, "source window origin is not finite");
+    if (!(std::isfinite(p->px) && p->px > 0) || !(std::isfinite(p->py) && p->py > 0))
+        return set_error(RAYSH_EINVAL, "pixel size must be finite and > 0");
+    if (p->nx <= 0 || p->ny <= 0) return set_error(RAYSH_EINVAL, "pixel counts must be > 0");
+    if ((int64_t)p->ny > kMaxRays / (int64_t)p->nx)
+        return set_error(RAYSH_EOVERFLOW, "more than 2^31-1 pixels");
+    if (!std::isfinite(p->x0 + p->nx * p->px) || !std::isfinite(p->y0 + p->ny * p->py))
+        return set_error(RAYSH_EINVAL, "source window is not finite");
+    return RAYSH_OK;
+}
+
+int validate_precision(int precision) {
+    if (precision != RAYSH_FP64 && precision != RAYSH_FP32_BULK)
+        return set_error(RAYSH_EINVAL, "unknown precision %d", precision);
+    return RAYSH_OK;
+}
+
+int validate_device_ptr(const void *ptr, size_t bytes, int device, const char *name) {
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(RAYSH_EINVAL, "%s is not device memory", name);
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return set_error(RAYSH_EINVAL, "%s is not device memory", name);
+    if (attr.device != device)
+        return set_error(RAYSH_EINVAL, "%s is on device %d, the context on %d", name, attr.device,
+                         device);
+    void *base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, const_cast<void *>(ptr));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(RAYSH_EINVAL, "%s: cannot query its allocation", name);
+    }
+    const size_t off = (size_t)((const char *)ptr - (const char *)base);
+    if (off > size || size - off < bytes)
+        return set_error(RAYSH_EINVAL, "%s holds %zu bytes, %zu needed", name, size - off, bytes);
+    return RAYSH_OK;
+}
+
+void fill_shoot_params(ShootParams &p, const raysh_ctx *c, const raysh_rays *r,
+                       const raysh_pixels *w) {
+    p.k11 = c->k11;
+    p.k12 = c->k12;
+    p.k22 = c->k22;
+    p.stars = c->d_stars;
+    p.n_stars = (int32_t)c->n_stars;
+    p.x0 = r->x0;
+    p.y0 = r->y0;
+    p.dx = r->dx;
+    p.dy = r->dy;
+    p.nx = r->nx;
+    p.ny = r->ny;
+    p.i0 = r->i0;
+    p.j0 = r->j0;
+    p.X0 = w->x0;
+    p.Y0 = w->y0;
+    p.Px = w->px;
+    p.Py = w->py;
+    p.NX = w->nx;
+    p.NY = w->ny;
+}
+
+extern "C" {
+
+const char *raysh_last_error(void) { return g_err; }
+
+int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_stream) {
+    if (!out) return set_error(RAYSH_EINVAL, "out is NULL");
+    if (!lens) return set_error(RAYSH_EINVAL, "lens is NULL");
+    if (!std::isfinite(lens->kappa_c) || !std::isfinite(lens->gamma1) || !std::isfinite(lens->gamma2))
+        return set_error(RAYSH_EINVAL, "kappa_c and gamma must be finite");
+    if (lens->n_stars < 0) return set_error(RAYSH_EINVAL, "n_stars < 0");
+    if (lens->n_stars > std::numeric_limits<int32_t>::max())
+        return set_error(RAYSH_EOVERFLOW, "n_stars > 2^31-1");
+    const int64_t n = lens->n_stars;
+    if (n > 0 && (!lens->x || !lens->y || !lens->m)) return set_error(RAYSH_EINVAL, "star array is NULL");
+    for (int64_t k = 0; k < n; ++k) {
+        if (!std::isfinite(lens->x[k]) || !std::isfinite(lens->y[k]))
+            return set_error(RAYSH_EINVAL, "star %lld position is not finite", (long long)k);
+        if (!std::isfinite(lens->m[k]) || lens->m[k] < 0)
+            return set_error(RAYSH_EINVAL, "star %lld mass is negative or not finite", (long long)k);
+    }
+    if (device < 0) return set_error(RAYSH_EINVAL, "device < 0");
+    int n_dev = 0;
+    hipError_t e = hipGetDeviceCount(&n_dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDeviceCount");
+    if (device >= n_dev) return set_error(RAYSH_EINVAL, "device %d of %d", device, n_dev);
+
+    DeviceGuard g(device);
+    if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", device);
+    raysh_ctx *c = new raysh_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->n_stars = n;
+    c->kappa_c = lens->kappa_c;
+    c->gamma1 = lens->gamma1;
+    c->gamma2 = lens->gamma2;
+    c->k11 = lens->kappa_c + lens->gamma1;
+    c->k12 = lens->gamma2;
+    c->k22 = lens->kappa_c - lens->gamma1;
+
+    std::vector<Star> host((size_t)(n > 0 ? n : 1), Star{0, 0, 0, 0});
+    for (int64_t k = 0; k < n; ++k) host[(size_t)k] = Star{lens->x[k], lens->y[k], lens->m[k], 0.0};
+    e = hipMalloc(&c->d_stars, host.size() * sizeof(Star));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return set_error(RAYSH_ENOMEM, "device allocation of %zu stars failed", host.size());
+    }
+    e = hipMalloc(&c->d_counter, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipHostMalloc(&c->h_counter, sizeof(unsigned long long), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_stars, host.data(), host.size() * sizeof(Star), hipMemcpyHostToDevice,
+                           c->stream);
+    // the host staging vector dies with this call
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        int code = hip_error(e, "raysh_init");
+        raysh_free(c);
+        return code;
+    }
+    *out = c;
+    return set_ok();
+}
+
+int raysh_set_stream(raysh_ctx *ctx, void *hip_stream) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    ctx->stream = (hipStream_t)hip_stream;
+    return set_ok();
+}
+
+int64_t raysh_n_stars(const raysh_ctx *ctx) { return ctx ? ctx->n_stars : 0; }
+
+int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int star_tile) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    if (int r = validate_precision(precision)) return r;
+    if ((precision == RAYSH_FP64 && star_tile != 0) || (precision == RAYSH_FP32_BULK && share != 0))
+        return set_error(RAYSH_EINVAL, "a tile field that does not apply to precision %d is not 0",
+                         precision);
+    TileShape t{cx, cy, share, star_tile};
+    const bool supported = precision == RAYSH_FP64 ? raysh::fp64_shape_supported(t)
+                                                   : raysh::fp32_shape_supported(t);
+    if (!supported)
+        return set_error(RAYSH_EINVAL, "tile shape (%d, %d, %d, %d) is not built for precision %d", cx, cy,
+                    share, star_tile, precision);
+    ctx->shape[precision] = t;
+    return set_ok();
+}
+
+int raysh_get_tile(const raysh_ctx *ctx, int precision, int *cx, int *cy, int *share, int *star_tile) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    if (int r = validate_precision(precision)) return r;
+    const TileShape &t = ctx->shape[precision];
+    if (cx) *cx = t.cx;
+    if (cy) *cy = t.cy;
+    if (share) *share = t.share;
+    if (star_tile) *star_tile = t.star_tile;
+    return set_ok();
+}
+
+int raysh_shoot(raysh_ctx *ctx, const raysh_rays *rays, int precision, double *beta_x,
+                double *beta_y, const raysh_pixels *pix, int32_t *bin) {
+    if (int r = validate_rays(rays)) return r;
+    if (int r = validate_precision(precision)) return r;
+    if (bin && !pix) return set_error(RAYSH_EINVAL, "bin requested without a source window");
+    if (pix)
+        if (int r = validate_pixels(pix)) return r;
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    const int64_t n = rays->nx * rays->ny;
+    if (n == 0) return set_ok();
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    if (beta_x)
+        if (int r = validate_device_ptr(beta_x, (size_t)n * 8, ctx->device, "beta_x")) return r;
+    if (beta_y)
+        if (int r = validate_device_ptr(beta_y, (size_t)n * 8, ctx->device, "beta_y")) return r;
+    if (bin)
+        if (int r = validate_device_ptr(bin, (size_t)n * 4, ctx->device, "bin")) return r;
+    if (!beta_x && !beta_y && !bin) return set_ok();
+
+    static const raysh_pixels unit = {0.0, 0.0, 1.0, 1.0, 1, 1};
+    ShootParams p{};
+    fill_shoot_params(p, ctx, rays, pix ? pix : &unit);
+    p.beta_x = beta_x;
+    p.beta_y = beta_y;
+    p.bin = bin;
+    hipError_t e = launch(ctx, p, precision);
+    if (e != hipSuccess) return hip_error(e, "raysh_shoot launch");
+    return set_ok();
+}
+
+int raysh_map(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix, int precision,
+              int32_t *counts, uint64_t *n_binned) {
+    if (int r = validate_rays(rays)) return r;
+    if (int r = validate_pixels(pix)) return r;
+    if (int r = validate_precision(precision)) return r;
+    if (!counts) return set_error(RAYSH_EINVAL, "counts is NULL");
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    const size_t map_bytes = (size_t)pix->nx * (size_t)pix->ny * 4;
+    if (int r = validate_device_ptr(counts, map_bytes, ctx->device, "counts")) return r;
+    const int64_t n = rays->nx * rays->ny;
+    if (n == 0) {
+        if (n_binned) *n_binned = 0;
+        return set_ok();
+    }
+    ShootParams p{};
+    fill_shoot_params(p, ctx, rays, pix);
+    p.counts = counts;
+    hipError_t e = hipSuccess;
+    if (n_binned) {
+        p.n_binned = ctx->d_counter;
+        e = raysh::launch_zero_u64(ctx->d_counter, 1, ctx->stream);
+        if (e != hipSuccess) return hip_error(e, "raysh_map counter reset");
+    }
+    e = launch(ctx, p, precision);
+    if (e != hipSuccess) return hip_error(e, "raysh_map launch");
+    if (n_binned) {
+        e = hipMemcpyAsync(ctx->h_counter, ctx->d_counter, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_error(e, "raysh_map");
+        *n_binned = *ctx->h_counter;
+    }
+    return set_ok();
+}
+
+int raysh_sync(raysh_ctx *ctx) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_error(e, "raysh_sync");
+    return set_ok();
+}
+
+int raysh_free(raysh_ctx *ctx) {
+    if (!ctx) return set_ok();
+    raysh_forget_batches(ctx);
+    int code = RAYSH_OK;
+    {
+        DeviceGuard g(ctx->device);
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) code = RAYSH_EDEVICE;
+        if (ctx->d_stars) (void)hipFree(ctx->d_stars);
+        if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+        if (ctx->h_counter) (void)hipHostFree(ctx->h_counter);
+    }
+    delete ctx;
+    if (code != RAYSH_OK) return set_error(code, "raysh_free: pending device error");
+    return set_ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Internal declarations shared by the raysh HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "raysh.h"
+
+namespace raysh {
+
+// One star as the kernels read it: FP64 position, mass and a pad word so
+// that a record is 32 bytes (one scalar 8-dword load).
+struct Star {
+    double x, y, m, pad;
+};
+
+// Everything a shooting kernel needs for one (lens, ray block, window).
+// Passed by value: it lands in the kernel-argument segment and is read with
+// scalar loads.
+struct ShootParams {
+    // Eq. (3), first term: K = [[k11, k12], [k12, k22]]
+    double k11, k12, k22;
+    const Star *stars;
+    int32_t n_stars;
+    int32_t tiles_x;           // ray tiles per lattice row of this block
+    // ray lattice block
+    double x0, y0, dx, dy;
+    int64_t nx, ny, i0, j0;
+    // source window
+    double X0, Y0, Px, Py;
+    int32_t NX, NY;
+    // outputs (any may be null)
+    double *beta_x, *beta_y;
+    int32_t *bin;
+    int32_t *counts;
+    unsigned long long *n_binned;
+};
+
+// One parameter set of a batch: its shooting parameters and the range of
+// work items (ray tiles) it owns in the batch's queue order.
+struct BatchSet {
+    ShootParams p;
+    int64_t first_item;
+    int64_t n_items;
+};
+
+// Arguments of the persistent batch kernels.  Sets are ordered by
+// decreasing cost per tile (longest first), items numbered set after set.
+struct BatchArgs {
+    const BatchSet *sets;
+    int32_t n_sets;
+    int64_t total_items;
+    unsigned long long *queue;   // next item to hand out; zero before launch
+};
+
+// Launch shapes selectable per call (the autotuner's search space).
+struct TileShape {
+    int cx, cy;      // rays per lane along x and y
+    int share;       // stars sharing one reciprocal (FP64 path)
+    int star_tile;   // stars staged in LDS per pass (FP32-bulk path)
+};
+
+// Launchers (shoot_fp64.hip, shoot_fp32.hip).  Return hipSuccess or the
+// launch error; `shape` must be one the launcher supports.
+hipError_t launch_shoot_fp64(const ShootParams &p, const TileShape &shape, hipStream_t s);
+hipError_t launch_shoot_fp32(const ShootParams &p, const TileShape &shape, hipStream_t s);
+bool fp64_shape_supported(const TileShape &shape);
+// Compiled shapes: writes up to cap of them, returns how many exist.
+int fp64_shape_list(TileShape *out, int cap);
+int fp32_shape_list(TileShape *out, int cap);
+bool fp32_shape_supported(const TileShape &shape);
+int tile_width(const TileShape &shape);   // rays per tile along x (16 * cx)
+int tile_height(const TileShape &shape);  // rays per tile along y (16 * cy)
+
+hipError_t launch_batch_fp64(const BatchArgs &b, const TileShape &shape, int blocks, hipStream_t s);
+hipError_t launch_batch_fp32(const BatchArgs &b, const TileShape &shape, int blocks, hipStream_t s);
+int batch_fp64_blocks_per_cu(const TileShape &shape);
+int batch_fp32_blocks_per_cu(const TileShape &shape);
+
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+
+}  // namespace raysh

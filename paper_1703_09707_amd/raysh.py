@@ -1,0 +1,251 @@
+"""Python binding of libraysh (argument marshalling only).
+
+Every step of the computation runs in the library's HIP kernels; torch is
+used here only to allocate device memory and to name the HIP stream.  The
+functions mirror the C ABI of include/raysh.h: ``Context`` wraps
+raysh_init/raysh_free, ``Context.shoot`` raysh_shoot, ``Context.map``
+raysh_map and ``map_batch`` raysh_map_batch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libraysh.so")
+
+FP64 = 0
+FP32_BULK = 1
+PRECISIONS = {"fp64": FP64, "fp32_bulk": FP32_BULK, FP64: FP64, FP32_BULK: FP32_BULK}
+
+OK, EINVAL, EOVERFLOW, ENOMEM, EDEVICE = 0, 1, 2, 3, 4
+_CODES = {EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"}
+
+EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", "raysh_get_tile",
+           "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch", "raysh_sync", "raysh_free",
+           "raysh_last_error")
+
+
+class RayshError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Lens(ctypes.Structure):
+    _fields_ = [("kappa_c", ctypes.c_double), ("gamma1", ctypes.c_double),
+                ("gamma2", ctypes.c_double), ("n_stars", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("m", ctypes.c_void_p)]
+
+
+class Rays(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("i0", ctypes.c_int64), ("j0", ctypes.c_int64)]
+
+
+class Pixels(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("px", ctypes.c_double), ("py", ctypes.c_double),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libraysh.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1703_09707_amd/build.py "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    lib.raysh_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Lens), I, P]
+    lib.raysh_set_stream.argtypes = [P, P]
+    lib.raysh_n_stars.argtypes = [P]
+    lib.raysh_n_stars.restype = ctypes.c_int64
+    lib.raysh_set_tile.argtypes = [P, I, I, I, I, I]
+    lib.raysh_get_tile.argtypes = [P, I] + [ctypes.POINTER(I)] * 4
+    lib.raysh_autotune.argtypes = [P, ctypes.POINTER(Rays), ctypes.POINTER(Pixels), I, ctypes.c_char_p] + \
+        [ctypes.POINTER(I)] * 4
+    lib.raysh_shoot.argtypes = [P, ctypes.POINTER(Rays), I, P, P, ctypes.POINTER(Pixels), P]
+    lib.raysh_map.argtypes = [P, ctypes.POINTER(Rays), ctypes.POINTER(Pixels), I, P,
+                              ctypes.POINTER(ctypes.c_uint64)]
+    lib.raysh_map_batch.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(Rays),
+                                    ctypes.POINTER(Pixels), I, ctypes.POINTER(P)]
+    lib.raysh_sync.argtypes = [P]
+    lib.raysh_free.argtypes = [P]
+    lib.raysh_last_error.restype = ctypes.c_char_p
+    for name in ("raysh_init", "raysh_set_stream", "raysh_set_tile", "raysh_get_tile", "raysh_autotune",
+                 "raysh_shoot", "raysh_map", "raysh_map_batch", "raysh_sync", "raysh_free"):
+        getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def check(code):
+    if code != OK:
+        raise RayshError(code, load().raysh_last_error().decode())
+
+
+def rays_struct(r) -> Rays:
+    """From a workloads.RayGrid, a tuple (x0, y0, dx, dy, nx, ny, i0, j0) or Rays."""
+    if isinstance(r, Rays):
+        return r
+    t = r.as_tuple() if hasattr(r, "as_tuple") else tuple(r)
+    return Rays(float(t[0]), float(t[1]), float(t[2]), float(t[3]),
+                int(t[4]), int(t[5]), int(t[6]), int(t[7]))
+
+
+def pixels_struct(p) -> Pixels:
+    """From a workloads.PixelGrid, a tuple (X0, Y0, Px, Py, NX, NY) or Pixels."""
+    if p is None or isinstance(p, Pixels):
+        return p
+    t = p.as_tuple() if hasattr(p, "as_tuple") else tuple(p)
+    return Pixels(float(t[0]), float(t[1]), float(t[2]), float(t[3]), int(t[4]), int(t[5]))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("raysh needs a ROCm GPU; torch.cuda.is_available() is False")
+    return torch
+
+
+def _stream_handle(torch, device, stream):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A lens (kappa_c, gamma, stars) resident on one GPU (raysh_init)."""
+
+    def __init__(self, lens, device: int = 0, stream=None):
+        torch = _torch()
+        lib = load()
+        if hasattr(lens, "as_tuple"):
+            lens = lens.as_tuple()
+        kc, g1, g2, x, y, m = lens
+        self._x = np.ascontiguousarray(x, dtype=np.float64)
+        self._y = np.ascontiguousarray(y, dtype=np.float64)
+        self._m = np.ascontiguousarray(m, dtype=np.float64)
+        n = len(self._x)
+        if not (len(self._y) == n and len(self._m) == n):
+            raise ValueError("star arrays differ in length")
+        cl = Lens(float(kc), float(g1), float(g2), n,
+                  self._x.ctypes.data if n else None, self._y.ctypes.data if n else None,
+                  self._m.ctypes.data if n else None)
+        self.device = int(device)
+        self._ptr = ctypes.c_void_p()
+        check(lib.raysh_init(ctypes.byref(self._ptr), ctypes.byref(cl), self.device,
+                             _stream_handle(torch, self.device, stream)))
+        self.n_stars = n
+        self.lens = (float(kc), float(g1), float(g2))
+
+    @property
+    def handle(self):
+        if not self._ptr:
+            raise RuntimeError("context is closed")
+        return self._ptr
+
+    def set_stream(self, stream):
+        torch = _torch()
+        check(load().raysh_set_stream(self.handle, _stream_handle(torch, self.device, stream)))
+
+    def set_tile(self, precision, cx, cy, share=0, star_tile=0):
+        check(load().raysh_set_tile(self.handle, PRECISIONS[precision], cx, cy, share, star_tile))
+
+    def get_tile(self, precision):
+        v = [ctypes.c_int() for _ in range(4)]
+        check(load().raysh_get_tile(self.handle, PRECISIONS[precision], *[ctypes.byref(a) for a in v]))
+        return tuple(a.value for a in v)
+
+    def autotune(self, rays, pix, precision="fp64", cache_path=None):
+        """Time the compiled launch shapes on a sample of this block, keep
+        the fastest (raysh_autotune); returns (cx, cy, share, star_tile)."""
+        v = [ctypes.c_int() for _ in range(4)]
+        cp = cache_path.encode() if cache_path else None
+        check(load().raysh_autotune(self.handle, ctypes.byref(rays_struct(rays)),
+                                    ctypes.byref(pixels_struct(pix)), PRECISIONS[precision], cp,
+                                    *[ctypes.byref(a) for a in v]))
+        return tuple(a.value for a in v)
+
+    def shoot(self, rays, precision="fp64", pix=None, beta=True, bins=True):
+        """Per-ray (beta_x, beta_y, bin) device tensors of shape (ny, nx);
+        entries not requested are None."""
+        torch = _torch()
+        r = rays_struct(rays)
+        p = pixels_struct(pix)
+        shape = (int(r.ny), int(r.nx))
+        dev = torch.device("cuda", self.device)
+        bx = torch.empty(shape, dtype=torch.float64, device=dev) if beta else None
+        by = torch.empty(shape, dtype=torch.float64, device=dev) if beta else None
+        b = torch.empty(shape, dtype=torch.int32, device=dev) if (bins and p is not None) else None
+        check(load().raysh_shoot(self.handle, ctypes.byref(r), PRECISIONS[precision],
+                                 _ptr(bx), _ptr(by), ctypes.byref(p) if p is not None else None,
+                                 _ptr(b)))
+        return bx, by, b
+
+    def map(self, rays, pix, precision="fp64", counts=None, n_binned=False):
+        """Accumulate Algorithm 1's counts into `counts` (a new zero map when
+        None); returns counts, or (counts, rays binned by this call)."""
+        torch = _torch()
+        r = rays_struct(rays)
+        p = pixels_struct(pix)
+        if counts is None:
+            counts = torch.zeros((p.ny, p.nx), dtype=torch.int32, device=torch.device("cuda", self.device))
+        if counts.dtype != torch.int32 or not counts.is_contiguous() or counts.numel() != p.nx * p.ny:
+            raise ValueError("counts must be a contiguous int32 tensor of ny*nx elements")
+        nb = ctypes.c_uint64(0)
+        check(load().raysh_map(self.handle, ctypes.byref(r), ctypes.byref(p), PRECISIONS[precision],
+                               _ptr(counts), ctypes.byref(nb) if n_binned else None))
+        return (counts, int(nb.value)) if n_binned else counts
+
+    def sync(self):
+        check(load().raysh_sync(self.handle))
+
+    def close(self):
+        if self._ptr:
+            check(load().raysh_free(self._ptr))
+            self._ptr = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self._ptr:
+                load().raysh_free(self._ptr)
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def map_batch(contexts, rays, pix, precision="fp64", counts=None):
+    """raysh_map_batch over several contexts in one persistent launch.
+    rays and pix are per-set sequences; counts a per-set list of int32
+    device maps (new zero maps when None).  Returns the list of maps."""
+    torch = _torch()
+    n = len(contexts)
+    R = (Rays * n)(*[rays_struct(r) for r in rays])
+    P = (Pixels * n)(*[pixels_struct(p) for p in pix])
+    if counts is None:
+        counts = [torch.zeros((P[s].ny, P[s].nx), dtype=torch.int32,
+                              device=torch.device("cuda", contexts[s].device)) for s in range(n)]
+    H = (ctypes.c_void_p * n)(*[c.handle for c in contexts])
+    C = (ctypes.c_void_p * n)(*[c.data_ptr() for c in counts])
+    check(load().raysh_map_batch(H, n, R, P, PRECISIONS[precision], C))
+    return counts

@@ -1,0 +1,153 @@
+"""The C-ABI library: loads, exports what include/raysh.h declares, and
+rejects bad arguments before touching a device (CPU only)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1703_09707_amd import raysh as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "raysh.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(raysh_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return R.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(R.EXPORTS)
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(R.Lens) == 56
+    assert ctypes.sizeof(R.Rays) == 64
+    assert ctypes.sizeof(R.Pixels) == 40
+
+
+def _err(lib):
+    return lib.raysh_last_error().decode()
+
+
+def _init(lib, kc=0.1, g1=0.2, g2=0.0, xs=(0.0,), ys=(0.0,), ms=(1.0,), n=None):
+    arr = ctypes.c_double * max(len(xs), 1)
+    x, y, m = arr(*xs), arr(*ys), arr(*ms)
+    lens = R.Lens(kc, g1, g2, len(xs) if n is None else n, ctypes.addressof(x), ctypes.addressof(y),
+                  ctypes.addressof(m))
+    out = ctypes.c_void_p()
+    code = lib.raysh_init(ctypes.byref(out), ctypes.byref(lens), 0, None)
+    return code, out
+
+
+@pytest.mark.parametrize("kw,code,msg", [
+    (dict(kc=math.nan), R.EINVAL, "finite"),
+    (dict(g2=math.inf), R.EINVAL, "finite"),
+    (dict(n=-1), R.EINVAL, "n_stars"),
+    (dict(n=2 ** 31), R.EOVERFLOW, "n_stars"),
+    (dict(xs=(math.nan,)), R.EINVAL, "position"),
+    (dict(ys=(math.inf,)), R.EINVAL, "position"),
+    (dict(ms=(-1.0,)), R.EINVAL, "mass"),
+    (dict(ms=(math.nan,)), R.EINVAL, "mass"),
+])
+def test_init_rejects_bad_lens(lib, kw, code, msg):
+    got, out = _init(lib, **kw)
+    assert got == code
+    assert msg in _err(lib)
+    assert not out.value
+
+
+def test_init_null_arguments(lib):
+    lens = R.Lens(0.0, 0.0, 0.0, 0, None, None, None)
+    assert lib.raysh_init(None, ctypes.byref(lens), 0, None) == R.EINVAL
+    out = ctypes.c_void_p()
+    assert lib.raysh_init(ctypes.byref(out), None, 0, None) == R.EINVAL
+    lens = R.Lens(0.0, 0.0, 0.0, 3, None, None, None)
+    assert lib.raysh_init(ctypes.byref(out), ctypes.byref(lens), 0, None) == R.EINVAL
+    assert "NULL" in _err(lib)
+    lens = R.Lens(0.0, 0.0, 0.0, 0, None, None, None)
+    assert lib.raysh_init(ctypes.byref(out), ctypes.byref(lens), -1, None) == R.EINVAL
+
+
+GOOD_RAYS = R.Rays(-1.0, -1.0, 0.01, 0.01, 200, 200, 0, 0)
+GOOD_PIX = R.Pixels(-1.0, -1.0, 0.1, 0.1, 20, 20)
+
+
+@pytest.mark.parametrize("rays,code,msg", [
+    (R.Rays(math.nan, 0, 0.1, 0.1, 4, 4, 0, 0), R.EINVAL, "origin"),
+    (R.Rays(0, 0, 0.0, 0.1, 4, 4, 0, 0), R.EINVAL, "spacing"),
+    (R.Rays(0, 0, 0.1, -0.1, 4, 4, 0, 0), R.EINVAL, "spacing"),
+    (R.Rays(0, 0, math.inf, 0.1, 4, 4, 0, 0), R.EINVAL, "spacing"),
+    (R.Rays(0, 0, 0.1, 0.1, -4, 4, 0, 0), R.EINVAL, "counts"),
+    (R.Rays(0, 0, 0.1, 0.1, 4, 4, -1, 0), R.EINVAL, "offsets"),
+    (R.Rays(0, 0, 0.1, 0.1, 65536, 32768, 0, 0), R.EOVERFLOW, "2^31"),
+    (R.Rays(0, 0, 0.1, 0.1, 4, 4, 2 ** 53, 0), R.EOVERFLOW, "2^53"),
+    (R.Rays(0, 0, 1e305, 0.1, 4, 4, 2 ** 20, 0), R.EINVAL, "not finite"),
+])
+def test_shoot_and_map_reject_bad_rays(lib, rays, code, msg):
+    assert lib.raysh_shoot(None, ctypes.byref(rays), 0, None, None, ctypes.byref(GOOD_PIX), None) == code
+    assert msg in _err(lib)
+    dummy = ctypes.c_void_p(1)
+    assert lib.raysh_map(None, ctypes.byref(rays), ctypes.byref(GOOD_PIX), 0, dummy, None) == code
+
+
+@pytest.mark.parametrize("pix,code,msg", [
+    (R.Pixels(math.nan, 0, 0.1, 0.1, 4, 4), R.EINVAL, "origin"),
+    (R.Pixels(0, 0, 0.0, 0.1, 4, 4), R.EINVAL, "pixel size"),
+    (R.Pixels(0, 0, 0.1, 0.1, 0, 4), R.EINVAL, "pixel counts"),
+    (R.Pixels(0, 0, 0.1, 0.1, 4, -4), R.EINVAL, "pixel counts"),
+    (R.Pixels(0, 0, 0.1, 0.1, 65536, 65536), R.EOVERFLOW, "pixels"),
+    (R.Pixels(1e308, 0, 1e308, 0.1, 4, 4), R.EINVAL, "not finite"),
+])
+def test_map_rejects_bad_window(lib, pix, code, msg):
+    dummy = ctypes.c_void_p(1)
+    assert lib.raysh_map(None, ctypes.byref(GOOD_RAYS), ctypes.byref(pix), 0, dummy, None) == code
+    assert msg in _err(lib)
+
+
+def test_other_argument_errors(lib):
+    dummy = ctypes.c_void_p(1)
+    r, p = ctypes.byref(GOOD_RAYS), ctypes.byref(GOOD_PIX)
+    assert lib.raysh_map(None, r, p, 7, dummy, None) == R.EINVAL
+    assert "precision" in _err(lib)
+    assert lib.raysh_map(None, r, p, 0, None, None) == R.EINVAL
+    assert "counts" in _err(lib)
+    assert lib.raysh_map(None, r, p, 0, dummy, None) == R.EINVAL
+    assert "ctx" in _err(lib)
+    assert lib.raysh_shoot(None, r, 0, None, None, None, dummy) == R.EINVAL
+    assert "window" in _err(lib)
+    assert lib.raysh_map(None, None, p, 0, dummy, None) == R.EINVAL
+    assert lib.raysh_map(None, r, None, 0, dummy, None) == R.EINVAL
+    assert lib.raysh_map_batch(None, 1, None, None, 0, None) == R.EINVAL
+    sets = (ctypes.c_void_p * 1)(None)
+    rays = (R.Rays * 1)(GOOD_RAYS)
+    pix = (R.Pixels * 1)(GOOD_PIX)
+    cnt = (ctypes.c_void_p * 1)(1)
+    assert lib.raysh_map_batch(sets, 0, rays, pix, 0, cnt) == R.EINVAL
+    assert lib.raysh_map_batch(sets, 1, rays, pix, 0, cnt) == R.EINVAL
+    assert "context" in _err(lib)
+    assert lib.raysh_set_tile(None, 0, 2, 4, 2, 0) == R.EINVAL
+    assert lib.raysh_autotune(None, r, p, 0, None, None, None, None, None) == R.EINVAL
+    assert "ctx" in _err(lib)
+    assert lib.raysh_sync(None) == R.EINVAL
+    assert lib.raysh_free(None) == R.OK
+    assert lib.raysh_n_stars(None) == 0
+
+
+def test_python_binding_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError, match="GPU"):
+        R.Context((0.0, 0.0, 0.0, [], [], []))

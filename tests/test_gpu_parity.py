@@ -1,0 +1,339 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar (FP64): at most 1e-6 of rays in a different pixel than the oracle, and
+|beta_gpu - beta_oracle| <= 1e-12 S per ray, S = |theta| + |K theta| +
+sum_k m_k/r_k (the scale rounding errors of Eq. (1) follow).  FP32-bulk:
+at most 1e-4 of rays in a different pixel than FP64.  Integer invariants
+(band additivity, map = histogram of bins, batch = single) are exact.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import shooter as ora
+from paper_1703_09707_amd import raysh as R
+from paper_1703_09707_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_SHAPES = [(1, 4, 2), (2, 2, 2), (2, 4, 1), (2, 4, 2), (2, 4, 4), (4, 4, 2), (2, 8, 2)]
+FP32_SHAPES = [(2, 2, 128), (2, 4, 64), (2, 4, 128), (2, 4, 256), (4, 4, 128), (2, 8, 128)]
+BETA_TOL = 1e-12
+MISBIN_FP64 = 1e-6
+MISBIN_FP32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    return t
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ----------------------------------------------------------------- exact fixtures
+def test_golden_exact_tiny(torch):
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "exact_tiny.json")))
+    L, Rr, P = g["lens"], g["rays"], g["pix"]
+    lens = (L["kappa_c"], L["gamma1"], L["gamma2"], L["x"], L["y"], L["m"])
+    rays = tuple(Rr[k] for k in ("x0", "y0", "dx", "dy", "nx", "ny", "i0", "j0"))
+    pix = tuple(P[k] for k in ("X0", "Y0", "Px", "Py", "NX", "NY"))
+    want = np.array(g["bins"])
+    near = np.array(g["edge_distance"]) < 1e-9
+    with R.Context(lens) as ctx:
+        for shape in FP64_SHAPES:
+            ctx.set_tile("fp64", shape[0], shape[1], share=shape[2])
+            _, _, b = ctx.shoot(rays, "fp64", pix)
+            got = _np(b).ravel()
+            np.testing.assert_array_equal(got[~near], want[~near])
+            assert got[want == -1].tolist() == want[want == -1].tolist()
+            counts = _np(ctx.map(rays, pix, "fp64")).ravel()
+            if not near.any():
+                np.testing.assert_array_equal(counts, np.array(g["counts"]))
+
+
+@pytest.mark.parametrize("kc,g1,g2", [(0.25, 0.125, 0.0625), (0.5, -0.25, 0.1875)])
+def test_dyadic_sheet_exact(torch, kc, g1, g2):
+    """No stars: every beta and pixel is exact, so GPU equals oracle bit for bit."""
+    lens = (kc, g1, g2, [], [], [])
+    rays = (-2.0 - 1 / 64, -1.5 - 1 / 128, 1 / 32, 1 / 64, 128, 192, 0, 0)
+    pix = (-1.5, -1.25, 1 / 16, 1 / 8, 48, 20)
+    ox, oy, ob = ora.shoot(lens, rays, pix)
+    with R.Context(lens) as ctx:
+        for prec in ("fp64", "fp32_bulk"):
+            bx, by, b = ctx.shoot(rays, prec, pix)
+            np.testing.assert_array_equal(_np(bx), ox)
+            np.testing.assert_array_equal(_np(by), oy)
+            np.testing.assert_array_equal(_np(b), ob)
+
+
+# ----------------------------------------------------------------- small config
+@pytest.fixture(scope="module")
+def small():
+    return W.plain_fp64_small()
+
+
+@pytest.fixture(scope="module")
+def small_oracle(small):
+    lens, rays, pix = small.lens.as_tuple(), small.rays.as_tuple(), small.pix.as_tuple()
+    bx, by, b = ora.shoot(lens, rays, pix)
+    counts, n = ora.map_counts(lens, rays, pix)
+    s = ora.error_scale_block(lens, rays)
+    return bx, by, b, counts, n, s
+
+
+def test_small_config_fp64_per_ray(torch, small, small_oracle):
+    bx, by, b, _, _, s = small_oracle
+    with R.Context(small.lens) as ctx:
+        for shape in FP64_SHAPES:
+            _say("shape", shape)
+            ctx.set_tile("fp64", shape[0], shape[1], share=shape[2])
+            gx, gy, gb = ctx.shoot(small.rays, "fp64", small.pix)
+            gx, gy, gb = _np(gx), _np(gy), _np(gb)
+            assert np.all(np.abs(gx - bx) <= BETA_TOL * s)
+            assert np.all(np.abs(gy - by) <= BETA_TOL * s)
+            mis = np.count_nonzero(gb != b)
+            assert mis <= MISBIN_FP64 * b.size, (shape, mis)
+
+
+def test_small_config_fp64_map(torch, small, small_oracle):
+    _, _, _, counts, n, _ = small_oracle
+    with R.Context(small.lens) as ctx:
+        maps = []
+        for shape in FP64_SHAPES:
+            ctx.set_tile("fp64", shape[0], shape[1], share=shape[2])
+            m, nb = ctx.map(small.rays, small.pix, "fp64", n_binned=True)
+            m = _np(m)
+            assert nb == m.sum()
+            # misbinned rays: half the L1 distance of the maps plus the change of the binned total
+            assert 0.5 * (np.abs(m - counts).sum() + abs(nb - n)) <= MISBIN_FP64 * small.rays.n_rays
+            maps.append(m)
+        for m in maps[1:]:
+            np.testing.assert_array_equal(m, maps[0])
+
+
+def test_run_to_run_identical(torch, small):
+    with R.Context(small.lens) as ctx:
+        a = _np(ctx.map(small.rays, small.pix, "fp64"))
+        b = _np(ctx.map(small.rays, small.pix, "fp64"))
+        np.testing.assert_array_equal(a, b)
+        c = ctx.map(small.rays, small.pix, "fp64")
+        ctx.map(small.rays, small.pix, "fp64", counts=c)   # accumulates
+        np.testing.assert_array_equal(_np(c), 2 * a)
+
+
+@pytest.mark.parametrize("i0,j0,nx,ny", [(0, 0, 1, 1), (3, 5, 17, 3), (990, 0, 10, 1000),
+                                         (0, 999, 1000, 1), (123, 456, 77, 65), (0, 0, 33, 65)])
+def test_ragged_blocks(torch, small, small_oracle, i0, j0, nx, ny):
+    bx, by, b, _, _, s = small_oracle
+    blk = small.rays.block(i0, j0, nx, ny)
+    with R.Context(small.lens) as ctx:
+        for prec in ("fp64",):
+            gx, gy, gb = ctx.shoot(blk, prec, small.pix)
+            sl = (slice(j0, j0 + ny), slice(i0, i0 + nx))
+            assert np.all(np.abs(_np(gx) - bx[sl]) <= BETA_TOL * s[sl])
+            assert np.all(np.abs(_np(gy) - by[sl]) <= BETA_TOL * s[sl])
+            np.testing.assert_array_equal(_np(gb), b[sl])
+
+
+def test_empty_block_is_noop(torch, small):
+    with R.Context(small.lens) as ctx:
+        counts = torch.zeros((small.pix.NY, small.pix.NX), dtype=torch.int32, device="cuda")
+        _, nb = ctx.map(small.rays.block(0, 0, 0, 5), small.pix, "fp64", counts=counts, n_binned=True)
+        assert nb == 0 and int(counts.sum()) == 0
+        bx, by, b = ctx.shoot(small.rays.block(0, 0, 7, 0), "fp64", small.pix)
+        assert bx.numel() == 0
+
+
+def test_band_additivity(torch, small):
+    """map(lattice) = sum of maps of its row bands and column blocks, exactly."""
+    with R.Context(small.lens) as ctx:
+        full = _np(ctx.map(small.rays, small.pix, "fp64"))
+        acc = torch.zeros((small.pix.NY, small.pix.NX), dtype=torch.int32, device="cuda")
+        for j0, ny in ((0, 333), (333, 1), (334, 666)):
+            for i0, nx in ((0, 500), (500, 500)):
+                ctx.map(small.rays.block(i0, j0, nx, ny), small.pix, "fp64", counts=acc)
+        np.testing.assert_array_equal(_np(acc), full)
+
+
+def test_zero_stars_and_massless_star(torch, small):
+    """n_stars = 0 is a pure sheet; a massless star changes nothing."""
+    lens0 = (small.lens.kappa_c, small.lens.gamma1, small.lens.gamma2, [], [], [])
+    lens1 = (small.lens.kappa_c, small.lens.gamma1, small.lens.gamma2, [0.3], [0.7], [0.0])
+    rays = small.rays.block(100, 100, 200, 150)
+    ox, oy, ob = ora.shoot(lens0, rays.as_tuple(), small.pix.as_tuple())
+    for lens in (lens0, lens1):
+        with R.Context(lens) as ctx:
+            gx, gy, gb = ctx.shoot(rays, "fp64", small.pix)
+            np.testing.assert_array_equal(_np(gx), ox)
+            np.testing.assert_array_equal(_np(gy), oy)
+            np.testing.assert_array_equal(_np(gb), ob)
+
+
+def test_fp32_bulk_small(torch, small, small_oracle):
+    _, _, b, _, _, _ = small_oracle
+    with R.Context(small.lens) as ctx:
+        for shape in FP32_SHAPES:
+            ctx.set_tile("fp32_bulk", shape[0], shape[1], star_tile=shape[2])
+            _, _, gb = ctx.shoot(small.rays, "fp32_bulk", small.pix)
+            frac = np.count_nonzero(_np(gb) != b) / b.size
+            _say("fp32 shape", shape, "misbinned", frac)
+            assert frac <= MISBIN_FP32
+
+
+# ----------------------------------------------------------------- large configs
+def _sample(rng, nx, ny, n):
+    return rng.integers(0, nx, n), rng.integers(0, ny, n)
+
+
+def test_large_config_full_size(torch):
+    """8192^2 rays, 16384 stars, the launch the benchmark times: the map equals
+    the histogram of the per-ray bins, and sampled rays match the oracle."""
+    w = W.plain_fp64_large()
+    rng = np.random.default_rng(0)
+    ii, jj = _sample(rng, w.rays.nx, w.rays.ny, 1500)
+    ox, oy, ob = ora.shoot_list(w.lens.as_tuple(), w.rays.as_tuple(), w.pix.as_tuple(), ii, jj)
+    tx, ty = ora.image_angles(w.rays.as_tuple())
+    s = np.array([ora.error_scale(w.lens.as_tuple(), tx[i], ty[j])[0] for i, j in zip(ii[:200], jj[:200])])
+    with R.Context(w.lens) as ctx:
+        _say("map fp64")
+        m, nb = ctx.map(w.rays, w.pix, "fp64", n_binned=True)
+        _say("shoot fp64")
+        gx, gy, gb = ctx.shoot(w.rays, "fp64", w.pix)
+        hist = torch.bincount(gb[gb >= 0].long(), minlength=w.pix.NX * w.pix.NY)
+        assert torch.equal(hist.to(torch.int32).view(w.pix.NY, w.pix.NX), m)
+        assert nb == int((gb >= 0).sum())
+        sel_b = _np(gb[torch.as_tensor(jj, device="cuda"), torch.as_tensor(ii, device="cuda")])
+        assert np.count_nonzero(sel_b != ob) <= max(1, MISBIN_FP64 * len(ob))
+        sx = _np(gx[torch.as_tensor(jj[:200], device="cuda"), torch.as_tensor(ii[:200], device="cuda")])
+        sy = _np(gy[torch.as_tensor(jj[:200], device="cuda"), torch.as_tensor(ii[:200], device="cuda")])
+        assert np.all(np.abs(sx - ox[:200]) <= BETA_TOL * s)
+        assert np.all(np.abs(sy - oy[:200]) <= BETA_TOL * s)
+        del gx, gy
+        _say("fp32 bulk")
+        _, _, fb = ctx.shoot(w.rays, "fp32_bulk", w.pix)
+        frac = float((fb != gb).sum()) / gb.numel()
+        _say("large config fp32-bulk misbinned fraction", frac)
+        assert frac <= MISBIN_FP32
+        mean_mu = nb * w.rays.dx * w.rays.dy / (20.0 * 20.0)
+        _say("mean magnification", mean_mu, "sheet", W.mean_magnification(0.45, 0.35, 0.1))
+
+
+def test_precision_study_subtile(torch):
+    """262144 stars: FP32-bulk against FP64 on the central 2048^2 rays."""
+    w = W.precision_study()
+    sub = W.precision_subtile(w, 2048)
+    rng = np.random.default_rng(1)
+    ii, jj = _sample(rng, sub.nx, sub.ny, 64)
+    _, _, ob = ora.shoot_list(w.lens.as_tuple(), w.rays.as_tuple(), w.pix.as_tuple(),
+                              ii + sub.i0, jj + sub.j0)
+    with R.Context(w.lens) as ctx:
+        _say("fp64 subtile")
+        _, _, b64 = ctx.shoot(sub, "fp64", w.pix, beta=False)
+        _say("fp32 subtile")
+        _, _, b32 = ctx.shoot(sub, "fp32_bulk", w.pix, beta=False)
+        sel = _np(b64[torch.as_tensor(jj, device="cuda"), torch.as_tensor(ii, device="cuda")])
+        assert np.count_nonzero(sel != ob) == 0
+        frac = float((b32 != b64).sum()) / b64.numel()
+        _say("precision-study fp32-bulk misbinned fraction", frac)
+        assert frac <= MISBIN_FP32
+
+
+# ----------------------------------------------------------------- batch
+@pytest.fixture(scope="module")
+def small_batch():
+    return W.batch_workloads(n_sets=9, rays_per_side=700, npix=128, n_lo=50, n_hi=3000,
+                             seed=W.BASE_SEED + 77)
+
+
+def test_batch_equals_single(torch, small_batch):
+    ctxs = [R.Context(w.lens) for w in small_batch]
+    try:
+        for prec in ("fp64", "fp32_bulk"):
+            singles = [_np(c.map(w.rays, w.pix, prec)) for c, w in zip(ctxs, small_batch)]
+            maps = R.map_batch(ctxs, [w.rays for w in small_batch], [w.pix for w in small_batch], prec)
+            for s, m in zip(singles, maps):
+                np.testing.assert_array_equal(_np(m), s)
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_batch_graph_replays(torch, small_batch):
+    """The captured launch is replayed on later calls; every replay adds the
+    same counts, with other GPU work in between."""
+    ctxs = [R.Context(w.lens) for w in small_batch]
+    try:
+        rays = [w.rays for w in small_batch]
+        pix = [w.pix for w in small_batch]
+        want = [_np(c.map(w.rays, w.pix, "fp64")) for c, w in zip(ctxs, small_batch)]
+        maps = [torch.zeros((p.NY, p.NX), dtype=torch.int32, device="cuda") for p in pix]
+        for rep in range(1, 5):
+            R.map_batch(ctxs, rays, pix, "fp64", counts=maps)
+            junk = torch.randn(1 << 20, device="cuda").sum()   # unrelated eager work
+            torch.cuda.synchronize()
+            for m, wnt in zip(maps, want):
+                np.testing.assert_array_equal(_np(m), rep * wnt)
+            del junk
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_batch_with_empty_and_ragged_sets(torch, small_batch):
+    ctxs = [R.Context(w.lens) for w in small_batch[:3]]
+    try:
+        rays = [small_batch[0].rays.block(0, 0, 0, 10), small_batch[1].rays.block(5, 7, 33, 17),
+                small_batch[2].rays]
+        pix = [w.pix for w in small_batch[:3]]
+        maps = R.map_batch(ctxs, rays, pix, "fp64")
+        for c, r, p, m in zip(ctxs, rays, pix, maps):
+            np.testing.assert_array_equal(_np(m), _np(c.map(r, p, "fp64")))
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+# ----------------------------------------------------------------- errors on the device
+def test_device_pointer_errors(torch, small):
+    with R.Context(small.lens) as ctx:
+        host = np.zeros((small.pix.NY, small.pix.NX), np.int32)
+        lib = R.load()
+        r = R.rays_struct(small.rays)
+        p = R.pixels_struct(small.pix)
+        code = lib.raysh_map(ctx.handle, r, p, 0, host.ctypes.data, None)
+        assert code == R.EINVAL and "device memory" in lib.raysh_last_error().decode()
+        big = R.Pixels(-5.0, -5.0, 0.001, 0.001, 10000, 10000)   # 400 MB map
+        tiny = torch.zeros(16, dtype=torch.int32, device="cuda")
+        code = lib.raysh_map(ctx.handle, r, big, 0, tiny.data_ptr(), None)
+        assert code == R.EINVAL and "needed" in lib.raysh_last_error().decode()
+        assert int(tiny.abs().sum()) == 0
+        with pytest.raises(R.RayshError):
+            ctx.set_tile("fp64", 3, 3, share=2)
+
+
+# ----------------------------------------------------------------- autotuner
+def test_autotune_picks_compiled_shape_and_caches(torch, small, tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    with R.Context(small.lens) as ctx:
+        ref = _np(ctx.map(small.rays, small.pix, "fp64"))
+        t64 = ctx.autotune(small.rays, small.pix, "fp64", cache_path=cache)
+        assert t64[:3] in FP64_SHAPES and ctx.get_tile("fp64") == t64
+        np.testing.assert_array_equal(_np(ctx.map(small.rays, small.pix, "fp64")), ref)
+        t32 = ctx.autotune(small.rays, small.pix, "fp32_bulk", cache_path=cache)
+        assert (t32[0], t32[1], t32[3]) in FP32_SHAPES
+    lines = open(cache).read().split("\n")
+    assert len([l for l in lines if l.strip()]) == 2
+    with R.Context(small.lens) as ctx:   # a cache hit gives the same choice without timing
+        assert ctx.autotune(small.rays, small.pix, "fp64", cache_path=cache) == t64
+    assert len([l for l in open(cache).read().split("\n") if l.strip()]) == 2
