@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
     ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
     ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-sized buffer 3 times (the reference kernel for "
+                         "scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -85,6 +88,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = W.plain_fp64_large()
     inter = w.interactions
     ctx = raysh.Context(w.lens, device=0)
