@@ -13,7 +13,12 @@ FLOPs (10 per interaction: 2 subtractions, 2 multiplies and 1 add for r^2,
 peak; the kernel's own time comes from HIP events recorded on the stream the
 kernel runs on.
 
+Also reported: the 64-set batch in one graph-captured persistent launch
+(against single launches), and the FP32-bulk misbinned fraction on the
+262144-star precision-study subtile.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
+                       [--no-batch] [--no-precision]
 """
 import argparse
 import json
@@ -25,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_INTERACTION = 10
+PROFILE = os.path.join(ROOT, "profiles", "shoot_fp64_kernel_plain-fp64-large.txt")
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 
 
@@ -35,6 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-set batch timing")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision study")
     ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
     ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
     ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
@@ -42,6 +50,19 @@ def parse():
                     help="first copy a MIB-sized buffer 3 times (the reference kernel for "
                          "scaling HBM byte counters)")
     return ap.parse_args()
+
+
+def measured_traffic(workload_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel, or None when the kernel sources or the launch shape have
+    changed since the counters were taken."""
+    from paper_1703_09707_amd import rocprof_summary as RS
+    s = RS.read_summary(PROFILE)
+    if not s or "traffic_bytes_per_launch" not in s:
+        return None
+    if s.get("source_sha256") != RS.source_hash("shoot_fp64_kernel") or s.get("workload") != workload_tag:
+        return None
+    return float(s["traffic_bytes_per_launch"])
 
 
 def time_steps(torch, ctx, w, precision, counts, steps, warmup):
@@ -60,6 +81,61 @@ def time_steps(torch, ctx, w, precision, counts, steps, warmup):
     wall = time.perf_counter() - t0
     kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     return wall, kernel_ms
+
+
+def batch_section(torch, raysh, W):
+    """64 parameter sets of uneven star counts in one persistent,
+    graph-captured launch (replayed), against one single launch per set."""
+    sets = W.batch_workloads()
+    ctxs = [raysh.Context(x.lens) for x in sets]
+    rays = [x.rays for x in sets]
+    pix = [x.pix for x in sets]
+    inter = sum(x.interactions for x in sets)
+    out = {"workload": "batch-64: 64 sets x 4096^2 rays, 512^2 maps, N* %d..%d" % (
+        min(x.lens.n_stars for x in sets), max(x.lens.n_stars for x in sets)),
+        "interactions": inter}
+    for prec in ("fp64", "fp32_bulk"):
+        maps = [torch.zeros((p.NY, p.NX), dtype=torch.int32, device="cuda") for p in pix]
+        raysh.map_batch(ctxs, rays, pix, prec, counts=maps)      # builds and captures the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        raysh.map_batch(ctxs, rays, pix, prec, counts=maps)      # replay
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = {"value": inter / dt, "unit": "interactions/s", "seconds": dt,
+                     "tile": list(ctxs[0].get_tile(prec))}
+    t0 = time.perf_counter()
+    for c, x, p in zip(ctxs, rays, pix):
+        c.map(x, p, "fp64")
+    torch.cuda.synchronize()
+    single = time.perf_counter() - t0
+    out["fp64_single_launches"] = {"value": inter / single, "unit": "interactions/s", "seconds": single}
+    out["speedup_vs_plain_fp64"] = {p: single / out[p]["seconds"] for p in ("fp64", "fp32_bulk")}
+    for c in ctxs:
+        c.close()
+    return out
+
+
+def precision_section(torch, raysh, W):
+    """FP32-bulk against FP64, ray by ray, on the central 2048^2 rays of the
+    262144-star precision-study lattice."""
+    w = W.precision_study()
+    sub = W.precision_subtile(w, 2048)
+    with raysh.Context(w.lens) as ctx:
+        _, _, b64 = ctx.shoot(sub, "fp64", w.pix, beta=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, b32 = ctx.shoot(sub, "fp32_bulk", w.pix, beta=False)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ctx.shoot(sub, "fp64", w.pix, beta=False)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        frac = float((b32 != b64).sum()) / b64.numel()
+    return {"workload": "precision-study subtile: 2048^2 rays x 262144 stars",
+            "misbinned_fraction_fp32_bulk_vs_fp64": frac, "fp64_seconds": t64, "fp32_bulk_seconds": t32,
+            "speedup": t64 / t32}
 
 
 def cpu_baseline(w, side):
@@ -112,6 +188,8 @@ def main():
     ms_step = 1e3 * wall / args.steps
     k_avg = sum(kms) / len(kms)
     achieved = FLOP_PER_INTERACTION * inter / (k_avg * 1e-3) / 1e12
+    tile = ctx.get_tile("fp64")
+    tag = "plain-fp64-large tile %d,%d,%d,%d" % tile
 
     out = {
         "metric": "ray-star interactions/s at 1 GPU (FP64 backward ray shooting, Algorithm 1)",
@@ -130,11 +208,11 @@ def main():
                    "rays": [w.rays.nx, w.rays.ny], "map": [w.pix.NX, w.pix.NY],
                    "kappa_star": w.lens.kappa_star, "kappa_c": w.lens.kappa_c,
                    "gamma": [w.lens.gamma1, w.lens.gamma2],
-                   "tile_fp64": list(ctx.get_tile("fp64"))},
+                   "tile_fp64": list(tile)},
         "rays_per_s": w.rays.n_rays / (wall / args.steps),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "shoot_fp64_kernel",
+                     "traffic": measured_traffic(tag), "kernel": "shoot_fp64_kernel",
                      "kernel_ms": k_avg,
                      "flop_per_launch": FLOP_PER_INTERACTION * inter},
     }
@@ -153,6 +231,12 @@ def main():
             "misbinned_fraction_lower_bound": 0.5 * (l1 + dn) / w.rays.n_rays,
             "tile": list(ctx.get_tile("fp32_bulk"))}
     ctx.close()
+    if not args.no_batch:
+        print("# batch (64 sets)", file=sys.stderr, flush=True)
+        out["batch"] = batch_section(torch, raysh, W)
+    if not args.no_precision:
+        print("# precision study", file=sys.stderr, flush=True)
+        out["precision_study"] = precision_section(torch, raysh, W)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)

@@ -41,6 +41,7 @@
 #ifndef RAYSH_H
 #define RAYSH_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -123,6 +124,12 @@ int64_t raysh_n_stars(const raysh_ctx *ctx);
  * raysh_set_tile.  EINVAL if the shape is not compiled into the library.
  */
 int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int star_tile);
+
+/* The launch shapes compiled for `precision`: writes up to `cap` shapes as
+ * 4 ints each (cx, cy, share, star_tile) into `shapes` (may be NULL when
+ * cap is 0) and returns how many exist, or -RAYSH_EINVAL for an unknown
+ * precision or a negative cap. */
+int raysh_list_tiles(int precision, int32_t *shapes, int cap);
 int raysh_get_tile(const raysh_ctx *ctx, int precision, int *cx, int *cy, int *share,
                    int *star_tile);
 
@@ -185,6 +192,87 @@ int raysh_map(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix,
  */
 int raysh_map_batch(raysh_ctx *const *sets, int n_sets, const raysh_rays *rays,
                     const raysh_pixels *pix, int precision, int32_t *const *counts);
+
+/* ----------------------------------------------------------------------
+ * Learned surrogate: magnification histograms and a small network that
+ * predicts them from lens parameters.  Ray counts per pixel are
+ * proportional to magnification, and a finite source sees the map
+ * convolved with its profile (Sec. 1); many maps over a parameter grid
+ * feed the Bayesian Monte Carlo analysis the paper's introduction
+ * describes.
+ * ---------------------------------------------------------------------- */
+
+/* Device workspace, in bytes, that raysh_log_mag_histogram needs for an
+ * nx x ny map (0 for a non-positive size). */
+size_t raysh_histogram_workspace(int32_t nx, int32_t ny);
+
+/*
+ * raysh_log_mag_histogram: histogram of log10(mu_sigma / mu_ref) over a map.
+ *   counts: device int32 map [ny][nx] (as written by raysh_map);
+ *   norm:   (dx*dy)/(px*py) of the lattice and window, so that
+ *           mu = counts * norm is the magnification;
+ *   sigma:  width of the circular Gaussian source, in angle units; the
+ *           profile is sampled at pixel offsets |k| <= ceil(3 sigma / p),
+ *           normalised per axis and applied separably; only pixels at least
+ *           that far from every edge are counted;
+ *   bins:   nbins uniform bins on [lo, hi); values below lo (mu_sigma = 0
+ *           too) go to the first bin, values at or above hi to the last.
+ * Outputs (device): bin_counts uint32[nbins] (overwritten) and, if not NULL,
+ * hist float[nbins] = bin_counts / their sum.  workspace: device memory of
+ * raysh_histogram_workspace(nx, ny) bytes.  All arithmetic is FP64.
+ * Asynchronous on hip_stream (NULL = null stream), on the counts' device.
+ * EINVAL on a bad size, range or pointer, or when no pixel lies 3 sigma
+ * inside the map; EOVERFLOW above 2^31-1 pixels.
+ */
+int raysh_log_mag_histogram(const int32_t *counts, int32_t nx, int32_t ny, double norm, double sigma,
+                            double px, double py, double mu_ref, int32_t nbins, double lo, double hi,
+                            void *workspace, size_t workspace_bytes, uint32_t *bin_counts, float *hist,
+                            void *hip_stream);
+
+/*
+ * The network: layers n_in -> n_hidden -> n_hidden -> n_out, GELU (erf
+ * form) after the first two, softmax output.  Weights are used in BF16,
+ * rounded to nearest-even from FP32 master copies; activations and sums are
+ * FP32.  Parameters are FP32, flat: W1[n_in][n_hidden], b1[n_hidden],
+ * W2[n_hidden][n_hidden], b2[n_hidden], W3[n_hidden][n_out], b3[n_out].
+ */
+typedef struct raysh_mlp raysh_mlp;
+
+/* Create the network on `device`, work on hip_stream, with host initial
+ * parameters `params` (copied) and room for batches up to max_batch.
+ * EINVAL on sizes < 1 or > 4096 (max_batch > 2^20), NULL or non-finite
+ * params; ENOMEM; EDEVICE. */
+int raysh_mlp_create(raysh_mlp **out, int device, void *hip_stream, int32_t n_in, int32_t n_hidden,
+                     int32_t n_out, int32_t max_batch, const float *params);
+
+/* Number of parameters (0 for NULL). */
+int64_t raysh_mlp_n_params(const raysh_mlp *mlp);
+
+/* Copy the FP32 master parameters to host memory (synchronous). */
+int raysh_mlp_get_params(const raysh_mlp *mlp, float *params);
+
+/* Softmax outputs for x (device float[batch][n_in]) into probs (device
+ * float[batch][n_out]); 1 <= batch <= max_batch. */
+int raysh_mlp_forward(raysh_mlp *mlp, const float *x, int32_t batch, float *probs);
+
+/* Cross-entropy -mean_b sum_j target_bj log p_bj against target (device
+ * float[batch][n_out]) and its gradient with respect to the parameters,
+ * kept for raysh_mlp_adam_step and, if grads (device float[n_params]) is not
+ * NULL, copied there; loss (device float, may be NULL) receives the loss.
+ * The BF16 rounding of the weights is passed straight through. */
+int raysh_mlp_gradient(raysh_mlp *mlp, const float *x, const float *target, int32_t batch, float *grads,
+                       float *loss);
+
+/* One bias-corrected Adam step with the last gradient. */
+int raysh_mlp_adam_step(raysh_mlp *mlp, float lr, float beta1, float beta2, float eps);
+
+/* raysh_mlp_gradient followed by raysh_mlp_adam_step. */
+int raysh_mlp_train_step(raysh_mlp *mlp, const float *x, const float *target, int32_t batch, float lr,
+                         float beta1, float beta2, float eps, float *loss);
+
+/* Wait for the network's work; release it (NULL is a no-op). */
+int raysh_mlp_sync(raysh_mlp *mlp);
+int raysh_mlp_free(raysh_mlp *mlp);
 
 /* Wait for all work enqueued by the context. */
 int raysh_sync(raysh_ctx *ctx);

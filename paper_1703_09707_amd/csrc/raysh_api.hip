@@ -220,6 +220,23 @@ int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int
     return set_ok();
 }
 
+int raysh_list_tiles(int precision, int32_t *shapes, int cap) {
+    if (validate_precision(precision) != RAYSH_OK || cap < 0 || (cap > 0 && !shapes)) {
+        set_error(RAYSH_EINVAL, "raysh_list_tiles: bad precision, cap or NULL shapes");
+        return -RAYSH_EINVAL;
+    }
+    TileShape t[64];
+    const int n = precision == RAYSH_FP64 ? raysh::fp64_shape_list(t, 64) : raysh::fp32_shape_list(t, 64);
+    for (int i = 0; i < n && i < cap && i < 64; ++i) {
+        shapes[4 * i + 0] = t[i].cx;
+        shapes[4 * i + 1] = t[i].cy;
+        shapes[4 * i + 2] = t[i].share;
+        shapes[4 * i + 3] = t[i].star_tile;
+    }
+    set_ok();
+    return n;
+}
+
 int raysh_get_tile(const raysh_ctx *ctx, int precision, int *cx, int *cy, int *share, int *star_tile) {
     if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
     if (int r = validate_precision(precision)) return r;

@@ -3,9 +3,11 @@
 //
 // Sec. 2.2 of arXiv:1703.09707 notes that grids of independent simulations
 // over (<M>, gamma, kappa_*, kappa_c) are common; here they share one
-// launch.  Work items are (set, ray tile); sets are ordered by decreasing
-// cost per tile (stars x rays per tile), so the queue hands out the longest
-// items first and the short ones fill the tail.
+// launch.  Work items are (set, run of consecutive ray tiles); sets are
+// ordered by decreasing cost per tile (stars x rays per tile), so the queue
+// hands out the longest items first and the short ones fill the tail.  Sets
+// with few stars get several tiles per item so that every item carries
+// about 2^25 ray-star interactions.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -63,6 +65,8 @@ struct BatchPlan {
     }
 };
 
+constexpr int64_t kItemWork = int64_t(1) << 25;   // ray-star interactions per queue item
+
 std::mutex g_mu;
 std::vector<BatchPlan *> g_plans;   // most recently used last
 constexpr size_t kMaxPlans = 8;
@@ -96,8 +100,13 @@ int build_plan(BatchPlan *plan, raysh_ctx *const *sets, int n_sets, const raysh_
         b.p.counts = counts[s];
         const int64_t tx = (r.nx + tw - 1) / tw, ty = (r.ny + th - 1) / th;
         b.p.tiles_x = (int32_t)tx;
+        b.n_tiles = tx * ty;
+        // an item covers enough tiles for ~kItemWork ray-star interactions,
+        // so the queue's atomic and barrier stay small beside the work
+        const int64_t per_tile = (int64_t)tw * th * std::max<int64_t>(sets[s]->n_stars, 1);
+        b.tiles_per_item = (int32_t)std::min<int64_t>(std::max<int64_t>(kItemWork / per_tile, 1), 64);
         b.first_item = items;
-        b.n_items = tx * ty;
+        b.n_items = (b.n_tiles + b.tiles_per_item - 1) / b.tiles_per_item;
         items += b.n_items;
         host.push_back(b);
     }

@@ -42,6 +42,8 @@ struct BatchSet {
     ShootParams p;
     int64_t first_item;
     int64_t n_items;
+    int64_t n_tiles;          // ray tiles of the set
+    int32_t tiles_per_item;   // consecutive tiles one item covers
 };
 
 // Arguments of the persistent batch kernels.  Sets are ordered by

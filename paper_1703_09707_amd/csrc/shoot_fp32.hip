@@ -9,7 +9,9 @@
 //     the differences taken in FP64 before rounding, so that stars near the
 //     tile keep full FP32 relative accuracy;
 //   - every lane reads each staged star as one LDS broadcast and forms the
-//     term with FP32 FMAs and the hardware FP32 reciprocal;
+//     term with FP32 FMAs and the hardware FP32 reciprocal (the mass
+//     multiplies the per-column and per-row offsets when a lane owns more
+//     rays than it has rows plus columns);
 //   - the FP32 partial sums of one staged tile are added to FP64 sums before
 //     the next tile, stars in index order throughout.
 #include "ray_common.h"
@@ -24,6 +26,8 @@ template <int CX, int CY, int S>
 __device__ __forceinline__ void fp32_tile(const ShootParams &p, BinShared &sh, float4 *stage,
                                           int64_t tile) {
     static_assert(S <= kThreads, "one star per thread when staging");
+    // mass folded into the per-column and per-row offsets when cheaper
+    constexpr bool FOLD = CX * CY > CX + CY;
     const int lx = threadIdx.x % kLanesX;
     const int ly = threadIdx.x / kLanesX;
     const int64_t tile_i = (tile % p.tiles_x) * (kLanesX * CX);
@@ -72,22 +76,27 @@ __device__ __forceinline__ void fp32_tile(const ShootParams &p, BinShared &sh, f
 #pragma unroll 2
         for (int k = 0; k < cnt; ++k) {
             const float4 q = stage[k];
-            float ex[CX], ey[CY], ey2[CY];
+            float ex[CX], mex[CX], ey[CY], mey[CY], ey2[CY];
 #pragma unroll
-            for (int a = 0; a < CX; ++a) ex[a] = ox[a] - q.x;
+            for (int a = 0; a < CX; ++a) {
+                ex[a] = ox[a] - q.x;
+                mex[a] = FOLD ? q.z * ex[a] : ex[a];
+            }
 #pragma unroll
             for (int b = 0; b < CY; ++b) {
                 ey[b] = oy[b] - q.y;
                 ey2[b] = ey[b] * ey[b];
+                mey[b] = FOLD ? q.z * ey[b] : ey[b];
             }
 #pragma unroll
             for (int b = 0; b < CY; ++b) {
 #pragma unroll
                 for (int a = 0; a < CX; ++a) {
                     const float r2 = __builtin_fmaf(ex[a], ex[a], ey2[b]);
-                    const float w = q.z * __builtin_amdgcn_rcpf(r2);
-                    fx[b][a] = __builtin_fmaf(w, ex[a], fx[b][a]);
-                    fy[b][a] = __builtin_fmaf(w, ey[b], fy[b][a]);
+                    const float inv = __builtin_amdgcn_rcpf(r2);
+                    const float w = FOLD ? inv : q.z * inv;
+                    fx[b][a] = __builtin_fmaf(w, mex[a], fx[b][a]);
+                    fy[b][a] = __builtin_fmaf(w, mey[b], fy[b][a]);
                 }
             }
         }
@@ -124,8 +133,15 @@ __global__ __launch_bounds__(kThreads) void batch_fp32_kernel(BatchArgs b) {
         const long long item = s_item;
         if (item >= b.total_items) break;   // uniform: every wave leaves
         const int set = find_set(b, item);
-        fp32_tile<CX, CY, S>(b.sets[set].p, sh, stage, item - b.sets[set].first_item);
-        __syncthreads();
+        const BatchSet &bs = b.sets[set];
+        const int64_t t0 = (item - bs.first_item) * bs.tiles_per_item;
+        const int64_t t1 = t0 + bs.tiles_per_item < bs.n_tiles ? t0 + bs.tiles_per_item : bs.n_tiles;
+        for (int64_t t = t0; t < t1; ++t) {   // uniform trip count
+            fp32_tile<CX, CY, S>(bs.p, sh, stage, t);
+            __syncthreads();   // red, the window and the stage are reused
+            bin_shared_init(sh);
+        }
+        __syncthreads();   // s_item is rewritten
     }
 }
 
@@ -159,11 +175,13 @@ hipError_t launch(const ShootParams &p, hipStream_t s) {
 
 #define RAYSH_FP32_SHAPES(X) \
     X(2, 2, 128)             \
-    X(2, 4, 64)              \
     X(2, 4, 128)             \
-    X(2, 4, 256)             \
+    X(4, 4, 64)              \
     X(4, 4, 128)             \
-    X(2, 8, 128)
+    X(4, 4, 256)             \
+    X(2, 8, 128)             \
+    X(4, 8, 128)             \
+    X(8, 4, 128)
 
 int fp32_shape_list(TileShape *out, int cap) {
     int n = 0;

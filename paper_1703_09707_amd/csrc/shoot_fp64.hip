@@ -2,10 +2,10 @@
 // Algorithm 1).
 //
 // One workgroup of 256 lanes owns a tile of (16 CX) x (16 CY) rays; each lane
-// owns CX columns and CY rows of it, so the x offset theta_x - x_k and its
-// square are shared by the lane's CY rays of a column, and the y offset by
-// the CX rays of a row.  r^2 = (theta_x - x_k)^2 + (theta_y - y_k)^2 is formed
-// without contraction, exactly as the plain definition rounds it.
+// owns CX columns and CY rows of it, so the x offset theta_x - x_k is shared
+// by the lane's CY rays of a column, and the y offset and its square by the
+// CX rays of a row.  r^2 = (theta_x - x_k)^2 + (theta_y - y_k)^2 is one FMA
+// per ray on those shared values.
 //
 // Stars are read in index order with uniform loads (every lane reads the
 // same record), which the compiler turns into scalar loads: star data sits
@@ -15,12 +15,14 @@
 // The division m_k / r_k^2 of Eq. (3) uses the hardware reciprocal, which
 // is good to about 2^-24, refined by one Newton step.  SHARE stars share one
 // reciprocal: for two stars, y = 1 / (r_a^2 r_b^2) refined once, then
-// w_a = (m_a r_b^2) y and w_b = (m_b r_a^2) y; four stars do the same with a
-// product of four.  The relative error of each w is a few units in the last
-// place of FP64 (the refined reciprocal is good to about 2^-48).  A ray
+// 1/r_a^2 = r_b^2 y and 1/r_b^2 = r_a^2 y; four stars do the same with a
+// product of four.  The relative error of each 1/r^2 is a few units in the
+// last place of FP64 (the refined reciprocal is good to about 2^-48).  A ray
 // exactly on a star gets a zero product, an infinite or NaN weight and a
 // non-finite beta, and is dropped, as the plain definition drops it.
-// The accumulation alpha += w (theta - theta_k) is one FMA per component,
+// The mass multiplies either the per-column and per-row offsets (when a lane
+// owns more rays than it has rows plus columns) or 1/r^2 of each ray; the
+// accumulation alpha += (m/r^2)(theta - theta_k) is one FMA per component,
 // stars in index order.
 #include "ray_common.h"
 
@@ -28,18 +30,37 @@ namespace raysh {
 
 namespace {
 
-// Division m / r2 for a single star: refined hardware reciprocal.
-__device__ __forceinline__ double weight1(double m, double r2) {
-    double y = __builtin_amdgcn_rcp(r2);
-    double q = m * y;
-    const double e = __builtin_fma(-r2, q, m);
-    return __builtin_fma(e, y, q);
-}
-
-// r^2 from precomputed squares, rounded like ex*ex + ey*ey.
-__device__ __forceinline__ double add_rn(double a, double b) {
-#pragma clang fp contract(off)
-    return a + b;
+// 1 / r2[s] for SHARE stars from one hardware reciprocal (good to about
+// 2^-24) of their product, refined by one Newton step (to about 2^-48), then
+// multiplied back by the other factors.
+template <int SHARE>
+__device__ __forceinline__ void reciprocals(const double (&r2)[SHARE], double (&inv)[SHARE]) {
+    if constexpr (SHARE == 1) {
+        double y = __builtin_amdgcn_rcp(r2[0]);
+        const double e = __builtin_fma(-r2[0], y, 1.0);
+        inv[0] = __builtin_fma(y, e, y);
+    } else if constexpr (SHARE == 2) {
+        const double pr = r2[0] * r2[1];
+        double y = __builtin_amdgcn_rcp(pr);
+        const double e = __builtin_fma(-pr, y, 1.0);
+        y = __builtin_fma(y, e, y);
+        inv[0] = r2[1] * y;
+        inv[1] = r2[0] * y;
+    } else {
+        static_assert(SHARE == 4, "SHARE is 1, 2 or 4");
+        const double p01 = r2[0] * r2[1];
+        const double p23 = r2[2] * r2[3];
+        const double pr = p01 * p23;
+        double y = __builtin_amdgcn_rcp(pr);
+        const double e = __builtin_fma(-pr, y, 1.0);
+        y = __builtin_fma(y, e, y);
+        const double y01 = p23 * y;   // 1 / (r0^2 r1^2)
+        const double y23 = p01 * y;   // 1 / (r2^2 r3^2)
+        inv[0] = r2[1] * y01;
+        inv[1] = r2[0] * y01;
+        inv[2] = r2[3] * y23;
+        inv[3] = r2[2] * y23;
+    }
 }
 
 __device__ __forceinline__ double mul_rn(double a, double b) {
@@ -51,6 +72,9 @@ __device__ __forceinline__ double mul_rn(double a, double b) {
 // entry; every thread of the workgroup must call it.
 template <int CX, int CY, int SHARE>
 __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, int64_t tile) {
+    // Fold the mass into the per-column and per-row offsets when that takes
+    // fewer multiplies (CX + CY per star) than weighting every ray (CX * CY).
+    constexpr bool FOLD = CX * CY > CX + CY;
     const int lx = threadIdx.x % kLanesX;
     const int ly = threadIdx.x / kLanesX;
     const int64_t tile_i = (tile % p.tiles_x) * (kLanesX * CX);
@@ -71,65 +95,65 @@ __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, i
     const Star *__restrict__ st = p.stars;
     const int n = p.n_stars;
     int k = 0;
-    for (; k + SHARE <= n; k += SHARE) {
-        double sx[SHARE], sy[SHARE], sm[SHARE];
+    // star groups are double-buffered: the next group's scalar loads are in
+    // flight while the current group is computed (the index of the group
+    // after the last stays on the last, so every load is in bounds)
+    double sx[SHARE], sy[SHARE], sm[SHARE];
+    if (n >= SHARE) {
 #pragma unroll
         for (int s = 0; s < SHARE; ++s) {
-            sx[s] = st[k + s].x;
-            sy[s] = st[k + s].y;
-            sm[s] = st[k + s].m;
+            sx[s] = st[s].x;
+            sy[s] = st[s].y;
+            sm[s] = st[s].m;
         }
-        double ex[SHARE][CX], ex2[SHARE][CX], ey[SHARE][CY], ey2[SHARE][CY];
+    }
+    for (; k + SHARE <= n; k += SHARE) {
+        const int kn = (k + 2 * SHARE <= n) ? k + SHARE : k;
+        double nx[SHARE], ny[SHARE], nm[SHARE];
+#pragma unroll
+        for (int s = 0; s < SHARE; ++s) {
+            nx[s] = st[kn + s].x;
+            ny[s] = st[kn + s].y;
+            nm[s] = st[kn + s].m;
+        }
+        // per column: the x offset and (FOLD) the offset times the mass;
+        // per row: the square of the y offset and the y offset (times the mass)
+        double ex[SHARE][CX], mex[SHARE][CX], ey2[SHARE][CY], mey[SHARE][CY];
 #pragma unroll
         for (int s = 0; s < SHARE; ++s) {
 #pragma unroll
             for (int a = 0; a < CX; ++a) {
                 ex[s][a] = tx[a] - sx[s];
-                ex2[s][a] = mul_rn(ex[s][a], ex[s][a]);
+                mex[s][a] = FOLD ? sm[s] * ex[s][a] : ex[s][a];
             }
 #pragma unroll
             for (int b = 0; b < CY; ++b) {
-                ey[s][b] = ty[b] - sy[s];
-                ey2[s][b] = mul_rn(ey[s][b], ey[s][b]);
+                const double e = ty[b] - sy[s];
+                ey2[s][b] = mul_rn(e, e);
+                mey[s][b] = FOLD ? sm[s] * e : e;
             }
         }
 #pragma unroll
         for (int b = 0; b < CY; ++b) {
 #pragma unroll
             for (int a = 0; a < CX; ++a) {
-                double r2[SHARE], w[SHARE];
+                double r2[SHARE], inv[SHARE];
 #pragma unroll
-                for (int s = 0; s < SHARE; ++s) r2[s] = add_rn(ex2[s][a], ey2[s][b]);
-                if constexpr (SHARE == 1) {
-                    w[0] = weight1(sm[0], r2[0]);
-                } else if constexpr (SHARE == 2) {
-                    const double pr = r2[0] * r2[1];
-                    double y = __builtin_amdgcn_rcp(pr);
-                    const double e = __builtin_fma(-pr, y, 1.0);
-                    y = __builtin_fma(y, e, y);
-                    w[0] = (sm[0] * r2[1]) * y;
-                    w[1] = (sm[1] * r2[0]) * y;
-                } else {
-                    static_assert(SHARE == 4, "SHARE is 1, 2 or 4");
-                    const double p01 = r2[0] * r2[1];
-                    const double p23 = r2[2] * r2[3];
-                    const double pr = p01 * p23;
-                    double y = __builtin_amdgcn_rcp(pr);
-                    const double e = __builtin_fma(-pr, y, 1.0);
-                    y = __builtin_fma(y, e, y);
-                    const double y01 = p23 * y;   // 1 / (r0^2 r1^2)
-                    const double y23 = p01 * y;   // 1 / (r2^2 r3^2)
-                    w[0] = (sm[0] * r2[1]) * y01;
-                    w[1] = (sm[1] * r2[0]) * y01;
-                    w[2] = (sm[2] * r2[3]) * y23;
-                    w[3] = (sm[3] * r2[2]) * y23;
-                }
+                for (int s = 0; s < SHARE; ++s) r2[s] = __builtin_fma(ex[s][a], ex[s][a], ey2[s][b]);
+                reciprocals<SHARE>(r2, inv);
 #pragma unroll
                 for (int s = 0; s < SHARE; ++s) {
-                    ax[b][a] = __builtin_fma(w[s], ex[s][a], ax[b][a]);
-                    ay[b][a] = __builtin_fma(w[s], ey[s][b], ay[b][a]);
+                    const double w = FOLD ? inv[s] : sm[s] * inv[s];
+                    ax[b][a] = __builtin_fma(w, mex[s][a], ax[b][a]);
+                    ay[b][a] = __builtin_fma(w, mey[s][b], ay[b][a]);
                 }
             }
+        }
+#pragma unroll
+        for (int s = 0; s < SHARE; ++s) {
+            sx[s] = nx[s];
+            sy[s] = ny[s];
+            sm[s] = nm[s];
         }
     }
     for (; k < n; ++k) {   // remaining stars, one at a time, still in index order
@@ -141,8 +165,9 @@ __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, i
 #pragma unroll
             for (int a = 0; a < CX; ++a) {
                 const double ex = tx[a] - sx;
-                const double r2 = add_rn(mul_rn(ex, ex), ey2);
-                const double w = weight1(sm, r2);
+                double r2[1] = {__builtin_fma(ex, ex, ey2)}, inv[1];
+                reciprocals<1>(r2, inv);
+                const double w = sm * inv[0];
                 ax[b][a] = __builtin_fma(w, ex, ax[b][a]);
                 ay[b][a] = __builtin_fma(w, ey, ay[b][a]);
             }
@@ -172,8 +197,15 @@ __global__ __launch_bounds__(kThreads) void batch_fp64_kernel(BatchArgs b) {
         const long long item = s_item;
         if (item >= b.total_items) break;   // uniform: every wave leaves
         const int set = find_set(b, item);
-        fp64_tile<CX, CY, SHARE>(b.sets[set].p, sh, item - b.sets[set].first_item);
-        __syncthreads();   // s_item, red and the window are reused
+        const BatchSet &bs = b.sets[set];
+        const int64_t t0 = (item - bs.first_item) * bs.tiles_per_item;
+        const int64_t t1 = t0 + bs.tiles_per_item < bs.n_tiles ? t0 + bs.tiles_per_item : bs.n_tiles;
+        for (int64_t t = t0; t < t1; ++t) {   // uniform trip count
+            fp64_tile<CX, CY, SHARE>(bs.p, sh, t);
+            __syncthreads();   // red and the window are reused
+            bin_shared_init(sh);
+        }
+        __syncthreads();   // s_item is rewritten
     }
 }
 
@@ -211,8 +243,11 @@ hipError_t launch(const ShootParams &p, hipStream_t s) {
     X(2, 4, 1)               \
     X(2, 4, 2)               \
     X(2, 4, 4)               \
+    X(4, 2, 4)               \
     X(4, 4, 2)               \
-    X(2, 8, 2)
+    X(4, 4, 4)               \
+    X(2, 8, 2)               \
+    X(2, 8, 4)
 
 int fp64_shape_list(TileShape *out, int cap) {
     int n = 0;

@@ -23,9 +23,12 @@ PRECISIONS = {"fp64": FP64, "fp32_bulk": FP32_BULK, FP64: FP64, FP32_BULK: FP32_
 OK, EINVAL, EOVERFLOW, ENOMEM, EDEVICE = 0, 1, 2, 3, 4
 _CODES = {EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"}
 
-EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", "raysh_get_tile",
-           "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch", "raysh_sync", "raysh_free",
-           "raysh_last_error")
+EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", "raysh_list_tiles",
+           "raysh_get_tile", "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch",
+           "raysh_histogram_workspace", "raysh_log_mag_histogram", "raysh_mlp_create",
+           "raysh_mlp_n_params", "raysh_mlp_get_params", "raysh_mlp_forward", "raysh_mlp_gradient",
+           "raysh_mlp_adam_step", "raysh_mlp_train_step", "raysh_mlp_sync", "raysh_mlp_free",
+           "raysh_sync", "raysh_free", "raysh_last_error")
 
 
 class RayshError(RuntimeError):
@@ -57,10 +60,15 @@ _lib = None
 
 
 def load():
-    """Load libraysh.so; raises if it has not been built."""
+    """Load libraysh.so; raises if it has not been built.
+
+    torch is imported first: its wheel carries its own HIP runtime, and a
+    process must use one HIP runtime only, so libraysh binds to the one torch
+    has loaded instead of loading a second copy from the system."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (see above)
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1703_09707_amd/build.py "
                            "(or __graft_entry__.build()); there is no fallback path")
@@ -73,6 +81,29 @@ def load():
     lib.raysh_n_stars.restype = ctypes.c_int64
     lib.raysh_set_tile.argtypes = [P, I, I, I, I, I]
     lib.raysh_get_tile.argtypes = [P, I] + [ctypes.POINTER(I)] * 4
+    lib.raysh_list_tiles.argtypes = [I, ctypes.POINTER(ctypes.c_int32), I]
+    lib.raysh_list_tiles.restype = I
+    lib.raysh_histogram_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.raysh_histogram_workspace.restype = ctypes.c_size_t
+    D = ctypes.c_double
+    lib.raysh_log_mag_histogram.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, D, D, D, D,
+                                            ctypes.c_int32, D, D, P, ctypes.c_size_t, P, P, P]
+    lib.raysh_log_mag_histogram.restype = I
+    F = ctypes.c_float
+    lib.raysh_mlp_create.argtypes = [ctypes.POINTER(P), I, P, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, P]
+    lib.raysh_mlp_n_params.argtypes = [P]
+    lib.raysh_mlp_n_params.restype = ctypes.c_int64
+    lib.raysh_mlp_get_params.argtypes = [P, P]
+    lib.raysh_mlp_forward.argtypes = [P, P, ctypes.c_int32, P]
+    lib.raysh_mlp_gradient.argtypes = [P, P, P, ctypes.c_int32, P, P]
+    lib.raysh_mlp_adam_step.argtypes = [P, F, F, F, F]
+    lib.raysh_mlp_train_step.argtypes = [P, P, P, ctypes.c_int32, F, F, F, F, P]
+    lib.raysh_mlp_sync.argtypes = [P]
+    lib.raysh_mlp_free.argtypes = [P]
+    for name in ("raysh_mlp_create", "raysh_mlp_get_params", "raysh_mlp_forward", "raysh_mlp_gradient",
+                 "raysh_mlp_adam_step", "raysh_mlp_train_step", "raysh_mlp_sync", "raysh_mlp_free"):
+        getattr(lib, name).restype = I
     lib.raysh_autotune.argtypes = [P, ctypes.POINTER(Rays), ctypes.POINTER(Pixels), I, ctypes.c_char_p] + \
         [ctypes.POINTER(I)] * 4
     lib.raysh_shoot.argtypes = [P, ctypes.POINTER(Rays), I, P, P, ctypes.POINTER(Pixels), P]
@@ -228,6 +259,17 @@ class Context:
                 load().raysh_free(self._ptr)
         except Exception:
             pass
+
+
+def list_tiles(precision):
+    """Launch shapes compiled into the library: tuples (cx, cy, share, star_tile)."""
+    lib = load()
+    n = lib.raysh_list_tiles(PRECISIONS[precision], None, 0)
+    if n < 0:
+        check(-n)
+    buf = (ctypes.c_int32 * (4 * n))()
+    lib.raysh_list_tiles(PRECISIONS[precision], buf, n)
+    return [tuple(buf[4 * i:4 * i + 4]) for i in range(n)]
 
 
 def _ptr(t):

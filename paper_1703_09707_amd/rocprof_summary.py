@@ -1,0 +1,166 @@
+"""Short text summaries of rocprofv3 runs (rocpd SQLite databases).
+
+    python -m paper_1703_09707_amd.rocprof_summary --kernel shoot_fp64_kernel \\
+        --stats gpurun_out/prof_stats/bench_results.db \\
+        --fetch gpurun_out/prof_fetch/bench_results.db \\
+        --write gpurun_out/prof_write/bench_results.db \\
+        --valu gpurun_out/prof_valu/bench_results.db \\
+        --copy-mib 1024 --command "..." --out profiles/<kernel>_<workload>.txt
+
+HBM byte counters are scaled by what the same counter reads for a plain copy
+of a known size (bench.py --copy-calibration MIB copies MIB MiB three times):
+scale = expected KiB / measured KiB.  The summary records a SHA-256 of the
+kernel's sources so that a later change of the kernel invalidates it.
+"""
+import argparse
+import hashlib
+import os
+import sqlite3
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = {
+    "shoot_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+    "shoot_fp32_kernel": ["csrc/shoot_fp32.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+    "batch_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+    "batch_fp32_kernel": ["csrc/shoot_fp32.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+}
+
+
+def source_hash(kernel):
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _rows(db, sql, args=()):
+    con = sqlite3.connect(db)
+    try:
+        return con.execute(sql, args).fetchall()
+    finally:
+        con.close()
+
+
+def kernel_stats(db):
+    return _rows(db, "select name, total_calls, total_duration, average, percentage from top_kernels")
+
+
+def counter_values(db, name_like):
+    """{counter: [value per dispatch]} for kernels whose name contains name_like."""
+    out = {}
+    for name, counter, value in _rows(db, "select name, counter_name, counter_value from pmc_events "
+                                          "where name like ?", (f"%{name_like}%",)):
+        out.setdefault(counter, []).append(value)
+    return out
+
+
+def dispatch_waves(db, name_like):
+    """Waves of one dispatch of the kernel (grid size / 64)."""
+    rows = _rows(db, "select grid_size from counters_collection where kernel_name like ? limit 1",
+                 (f"%{name_like}%",))
+    return rows[0][0] / 64.0 if rows else None
+
+
+def read_summary(path):
+    """key: value pairs of a summary file (None if missing)."""
+    if not os.path.exists(path):
+        return None
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--valu")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--command", default="")
+    ap.add_argument("--workload", default="")
+    ap.add_argument("--flop-per-launch", type=float, default=None)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+
+    lines = [f"kernel: {a.kernel}", f"workload: {a.workload}", f"source_sha256: {source_hash(a.kernel)}",
+             f"command: {a.command}", ""]
+    lines.append("kernel trace (rocprofv3 --kernel-trace --stats), durations in us:")
+    k_avg = None
+    for name, calls, total, avg, pct in kernel_stats(a.stats)[:8]:
+        short = name.split("(")[0][-70:]
+        lines.append(f"  {short:70s} calls {calls:4d} avg {avg:14.1f} total {total:16.1f} {pct:6.2f}%")
+        if a.kernel in name and k_avg is None:
+            k_avg = avg
+    lines.append("")
+    lines.append(f"avg_us: {k_avg}")
+    expected_kib = a.copy_mib * 1024.0
+    traffic = 0.0
+    have = 0
+    for label, db, counter in (("fetch", a.fetch, "FETCH_SIZE"), ("write", a.write, "WRITE_SIZE")):
+        if not db:
+            continue
+        copy = counter_values(db, "copyBuffer").get(counter) or counter_values(db, "copy").get(counter)
+        kern = counter_values(db, a.kernel).get(counter)
+        if not copy or not kern:
+            continue
+        c = sum(copy) / len(copy)
+        k = sum(kern) / len(kern)
+        scale = expected_kib / c
+        lines.append(f"{label}_copy_kib_per_dispatch: {c:.1f}  (copy of {a.copy_mib} MiB: expected {expected_kib:.0f})")
+        lines.append(f"{label}_scale: {scale:.4f}")
+        lines.append(f"{label}_kib_per_dispatch: {k:.1f}")
+        lines.append(f"{label}_bytes_per_launch: {k * scale * 1024:.0f}")
+        traffic += k * scale * 1024
+        have += 1
+    if have == 2:
+        lines.append(f"traffic_bytes_per_launch: {traffic:.0f}")
+    if a.valu:
+        vals = counter_values(a.valu, a.kernel)
+        if vals:
+            lines.append("")
+            avg = {k: sum(v) / len(v) for k, v in vals.items()}
+            waves = dispatch_waves(a.valu, a.kernel)
+            # SQ counters are read from a subset of the shader engines; scale
+            # them by (waves of the dispatch) / (waves the counters saw)
+            factor = waves / avg["SQ_WAVES"] if waves and avg.get("SQ_WAVES") else 1.0
+            lines.append(f"dispatch_waves: {waves}")
+            lines.append(f"sq_sample_factor: {factor:.3f}  (dispatch waves / SQ_WAVES)")
+            lines.append("VALU counters per dispatch (wave instructions, raw; then x sq_sample_factor):")
+            for k in sorted(avg):
+                scaled = avg[k] * factor if k.startswith("SQ_") else avg[k]
+                lines.append(f"  {k}: {avg[k]:.6e}  ->  {scaled:.6e}")
+            avg = {k: (v * factor if k.startswith("SQ_") else v) for k, v in avg.items()}
+            f64 = 64 * (avg.get("SQ_INSTS_VALU_ADD_F64", 0) + avg.get("SQ_INSTS_VALU_MUL_F64", 0) +
+                        avg.get("SQ_INSTS_VALU_TRANS_F64", 0) + 2 * avg.get("SQ_INSTS_VALU_FMA_F64", 0))
+            lines.append(f"counter_flop_fp64_per_launch: {f64:.6e}")
+            if k_avg:
+                sec = k_avg * 1e-6
+                lines.append(f"counter_tflops_fp64: {f64 / sec / 1e12:.3f}")
+                if "GRBM_GUI_ACTIVE" in avg:
+                    clock = avg["GRBM_GUI_ACTIVE"] / sec
+                    lines.append(f"mean_clock_ghz: {clock / 1e9:.3f}  (GRBM_GUI_ACTIVE / kernel time)")
+                if "SQ_INSTS_VALU" in avg and waves:
+                    simds = 1024   # 256 CUs x 4 SIMDs
+                    busy = avg["SQ_INSTS_VALU"] * 4 / simds / sec
+                    lines.append(f"valu_issue_cycles_per_second_per_simd: {busy:.4e}  "
+                                 "(a wave64 VALU instruction takes 4 cycles of a 16-lane SIMD)")
+                    if "GRBM_GUI_ACTIVE" in avg:
+                        lines.append(f"valu_issue_fraction: {busy / clock:.3f}  (of the measured clock)")
+            if a.flop_per_launch:
+                lines.append(f"algorithmic_flop_per_launch: {a.flop_per_launch:.6e}")
+                lines.append(f"counter_over_algorithmic: {f64 / a.flop_per_launch:.4f}")
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

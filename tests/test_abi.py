@@ -31,6 +31,16 @@ def test_exports_every_declared_symbol(lib):
     assert set(names) == set(R.EXPORTS)
 
 
+def test_compiled_tile_lists():
+    f64 = R.list_tiles("fp64")
+    f32 = R.list_tiles("fp32_bulk")
+    assert len(f64) >= 5 and len(f32) >= 5
+    assert all(t[3] == 0 and t[2] in (1, 2, 4) for t in f64)
+    assert all(t[2] == 0 and t[3] > 0 for t in f32)
+    lib = R.load()
+    assert lib.raysh_list_tiles(5, None, 0) == -R.EINVAL
+
+
 def test_struct_layouts():
     assert ctypes.sizeof(R.Lens) == 56
     assert ctypes.sizeof(R.Rays) == 64
@@ -151,3 +161,37 @@ def test_python_binding_fails_loudly_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError, match="GPU"):
         R.Context((0.0, 0.0, 0.0, [], [], []))
+
+
+def test_histogram_and_mlp_argument_errors(lib):
+    D = 1.0
+    dummy = ctypes.c_void_p(1)
+    h = lib.raysh_log_mag_histogram
+    assert lib.raysh_histogram_workspace(0, 5) == 0
+    assert lib.raysh_histogram_workspace(10, 10) >= 800
+    args = dict(nx=64, ny=64, norm=0.5, sigma=0.1, px=0.1, py=0.1, mu_ref=1.0, nbins=64, lo=-2.0, hi=2.0)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return h(dummy, a["nx"], a["ny"], a["norm"], a["sigma"], a["px"], a["py"], a["mu_ref"],
+                 a["nbins"], a["lo"], a["hi"], dummy, 1 << 20, dummy, None, None)
+    for kw, msg in [(dict(nx=0), "map size"), (dict(norm=-1.0), "norm"), (dict(sigma=math.nan), "sigma"),
+                    (dict(px=0.0), "pixel"), (dict(mu_ref=0.0), "mu_ref"), (dict(nbins=0), "nbins"),
+                    (dict(lo=2.0, hi=-2.0), "range"), (dict(sigma=5.0), "larger than the map"),
+                    (dict(nx=65536, ny=65536), "2^31")]:
+        code = call(**kw)
+        assert code in (R.EINVAL, R.EOVERFLOW) and msg in _err(lib), (kw, _err(lib))
+    assert h(dummy, 64, 64, D, 0.1, 0.1, 0.1, D, 64, -2.0, 2.0, dummy, 16, dummy, None, None) == R.EINVAL
+    assert "workspace" in _err(lib)
+    out = ctypes.c_void_p()
+    p = (ctypes.c_float * 10)()
+    assert lib.raysh_mlp_create(ctypes.byref(out), 0, None, 0, 4, 4, 8, p) == R.EINVAL
+    assert lib.raysh_mlp_create(ctypes.byref(out), 0, None, 4, 4, 4, 8, None) == R.EINVAL
+    assert lib.raysh_mlp_create(None, 0, None, 4, 4, 4, 8, p) == R.EINVAL
+    nan = (ctypes.c_float * 64)(*([0.0] * 10 + [math.nan] + [0.0] * 53))   # 52 parameters
+    assert lib.raysh_mlp_create(ctypes.byref(out), 0, None, 2, 4, 4, 8, nan) == R.EINVAL
+    assert "not finite" in _err(lib)
+    assert lib.raysh_mlp_forward(None, dummy, 4, dummy) == R.EINVAL
+    assert lib.raysh_mlp_adam_step(None, 1e-3, 0.9, 0.999, 1e-8) == R.EINVAL
+    assert lib.raysh_mlp_free(None) == R.OK
+    assert lib.raysh_mlp_n_params(None) == 0
