@@ -152,15 +152,43 @@ __device__ __forceinline__ void finish_tile(const ShootParams &p, BinShared &sh,
     if (threadIdx.x == 0 && p.n_binned) atomicAdd(p.n_binned, (unsigned long long)total);
 }
 
+// Star records read through the constant address space: no kernel writes
+// them, and uniform loads from it become scalar loads whatever the kernel
+// stores elsewhere.
+typedef const __attribute__((address_space(4))) Star ConstStar;
+
+__device__ __forceinline__ const ConstStar *const_stars(const Star *p) {
+    return (const ConstStar *)p;
+}
+
+// A value every lane holds alike, moved to a scalar register.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Set owning queue item `item` (binary search over first_item; uniform).
-__device__ __forceinline__ int find_set(const BatchArgs &b, long long item) {
+__device__ __forceinline__ int find_set(const BatchArgs &b, int item) {
     int lo = 0, hi = b.n_sets - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) / 2;
         if (b.sets[mid].first_item <= item) lo = mid;
         else hi = mid - 1;
     }
-    return lo;
+    return uniform(lo);
+}
+
+// The set's parameters, copied word by word into scalar registers.
+__device__ __forceinline__ BatchSet load_set(const BatchSet *src) {
+    static_assert(sizeof(BatchSet) % 4 == 0, "BatchSet is a whole number of words");
+    BatchSet out;
+    const char *s = reinterpret_cast<const char *>(src);
+    char *d = reinterpret_cast<char *>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(BatchSet) / 4); ++i) {
+        int w;
+        __builtin_memcpy(&w, s + 4 * i, 4);
+        w = uniform(w);
+        __builtin_memcpy(d + 4 * i, &w, 4);
+    }
+    return out;
 }
 
 }  // namespace raysh

@@ -9,6 +9,7 @@
 // with few stars get several tiles per item so that every item carries
 // about 2^25 ray-star interactions.
 #include <algorithm>
+#include <limits>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -112,6 +113,8 @@ int build_plan(BatchPlan *plan, raysh_ctx *const *sets, int n_sets, const raysh_
     }
     plan->total_items = items;
     if (items == 0) return RAYSH_OK;
+    if (items > std::numeric_limits<int32_t>::max())
+        return set_error(RAYSH_EOVERFLOW, "raysh_map_batch: more than 2^31-1 work items");
 
     hipError_t e = hipMalloc(&plan->d_sets, host.size() * sizeof(BatchSet));
     if (e == hipSuccess) e = hipMalloc(&plan->d_queue, sizeof(unsigned long long));

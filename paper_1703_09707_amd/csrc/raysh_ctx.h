@@ -14,7 +14,7 @@ struct raysh_ctx {
     unsigned long long *d_counter = nullptr;
     unsigned long long *h_counter = nullptr;   // pinned
     // default launch shapes: the fastest on MI355X for the 16384-star workload
-    raysh::TileShape shape[2] = {{4, 4, 4, 0}, {4, 4, 0, 128}};
+    raysh::TileShape shape[2] = {{4, 4, 8, 0}, {4, 4, 0, 128}};
 };
 
 // Error reporting: store a message for raysh_last_error and return code.

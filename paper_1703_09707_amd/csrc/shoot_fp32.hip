@@ -130,10 +130,10 @@ __global__ __launch_bounds__(kThreads) void batch_fp32_kernel(BatchArgs b) {
         if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.queue, 1ull);
         bin_shared_init(sh);
         __syncthreads();
-        const long long item = s_item;
-        if (item >= b.total_items) break;   // uniform: every wave leaves
-        const int set = find_set(b, item);
-        const BatchSet &bs = b.sets[set];
+        const long long item_all = s_item;
+        if (item_all >= b.total_items) break;   // every wave reads the same value and leaves
+        const int item = uniform((int)item_all);
+        const BatchSet bs = load_set(&b.sets[find_set(b, item)]);
         const int64_t t0 = (item - bs.first_item) * bs.tiles_per_item;
         const int64_t t1 = t0 + bs.tiles_per_item < bs.n_tiles ? t0 + bs.tiles_per_item : bs.n_tiles;
         for (int64_t t = t0; t < t1; ++t) {   // uniform trip count
@@ -179,9 +179,7 @@ hipError_t launch(const ShootParams &p, hipStream_t s) {
     X(4, 4, 64)              \
     X(4, 4, 128)             \
     X(4, 4, 256)             \
-    X(2, 8, 128)             \
-    X(4, 8, 128)             \
-    X(8, 4, 128)
+    X(2, 8, 128)
 
 int fp32_shape_list(TileShape *out, int cap) {
     int n = 0;

@@ -13,13 +13,17 @@
 // VGPRs and no LDS traffic.
 //
 // The division m_k / r_k^2 of Eq. (3) uses the hardware reciprocal, which
-// is good to about 2^-24, refined by one Newton step.  SHARE stars share one
-// reciprocal: for two stars, y = 1 / (r_a^2 r_b^2) refined once, then
-// 1/r_a^2 = r_b^2 y and 1/r_b^2 = r_a^2 y; four stars do the same with a
-// product of four.  The relative error of each 1/r^2 is a few units in the
-// last place of FP64 (the refined reciprocal is good to about 2^-48).  A ray
-// exactly on a star gets a zero product, an infinite or NaN weight and a
-// non-finite beta, and is dropped, as the plain definition drops it.
+// is good to about 2^-24 and issues at a quarter of the FMA rate, refined by
+// one Newton step.  SHARE values of r^2 share one reciprocal: up to four
+// consecutive stars of one ray, or four stars times two neighbouring rays of
+// a row; 1/r^2 of each is recovered from the reciprocal of their product
+// through a product tree (for two: y = 1/(r_a^2 r_b^2), 1/r_a^2 = r_b^2 y,
+// 1/r_b^2 = r_a^2 y).  The relative error of each 1/r^2 is a few units in
+// the last place of FP64 (the refined reciprocal is good to about 2^-48).
+// The product of eight r^2 stays in FP64 range for separations between
+// about 1e-19 and 1e19.  A ray exactly on a star gets a zero product, an
+// infinite or NaN weight and a non-finite beta, and is dropped, as the plain
+// definition drops it.
 // The mass multiplies either the per-column and per-row offsets (when a lane
 // owns more rays than it has rows plus columns) or 1/r^2 of each ray; the
 // accumulation alpha += (m/r^2)(theta - theta_k) is one FMA per component,
@@ -30,37 +34,38 @@ namespace raysh {
 
 namespace {
 
-// 1 / r2[s] for SHARE stars from one hardware reciprocal (good to about
-// 2^-24) of their product, refined by one Newton step (to about 2^-48), then
-// multiplied back by the other factors.
-template <int SHARE>
-__device__ __forceinline__ void reciprocals(const double (&r2)[SHARE], double (&inv)[SHARE]) {
-    if constexpr (SHARE == 1) {
-        double y = __builtin_amdgcn_rcp(r2[0]);
-        const double e = __builtin_fma(-r2[0], y, 1.0);
-        inv[0] = __builtin_fma(y, e, y);
-    } else if constexpr (SHARE == 2) {
-        const double pr = r2[0] * r2[1];
-        double y = __builtin_amdgcn_rcp(pr);
-        const double e = __builtin_fma(-pr, y, 1.0);
-        y = __builtin_fma(y, e, y);
-        inv[0] = r2[1] * y;
-        inv[1] = r2[0] * y;
+// 1 / r[i] for N values from one hardware reciprocal (good to about 2^-24)
+// of their product, refined by one Newton step (to about 2^-48).  The
+// product is built as a balanced tree (N - 1 multiplies); walking the tree
+// back down, each node's inverse times its sibling's product is the inverse
+// of the node's other child (2 multiplies per node), so the leaves receive
+// 1 / r[i].  Cost: 3 (N - 1) multiplies, one reciprocal, two FMAs.
+template <int N>
+__device__ __forceinline__ double tree_product(const double *r) {
+    if constexpr (N == 1) return r[0];
+    else return tree_product<N / 2>(r) * tree_product<N / 2>(r + N / 2);
+}
+
+template <int N>
+__device__ __forceinline__ void tree_inverse(const double *r, double y, double *inv) {
+    if constexpr (N == 1) {
+        inv[0] = y;
     } else {
-        static_assert(SHARE == 4, "SHARE is 1, 2 or 4");
-        const double p01 = r2[0] * r2[1];
-        const double p23 = r2[2] * r2[3];
-        const double pr = p01 * p23;
-        double y = __builtin_amdgcn_rcp(pr);
-        const double e = __builtin_fma(-pr, y, 1.0);
-        y = __builtin_fma(y, e, y);
-        const double y01 = p23 * y;   // 1 / (r0^2 r1^2)
-        const double y23 = p01 * y;   // 1 / (r2^2 r3^2)
-        inv[0] = r2[1] * y01;
-        inv[1] = r2[0] * y01;
-        inv[2] = r2[3] * y23;
-        inv[3] = r2[2] * y23;
+        const double lo = tree_product<N / 2>(r);       // common subexpressions of the up-sweep
+        const double hi = tree_product<N / 2>(r + N / 2);
+        tree_inverse<N / 2>(r, hi * y, inv);           // 1 / (product of the lower half)
+        tree_inverse<N / 2>(r + N / 2, lo * y, inv + N / 2);
     }
+}
+
+template <int N>
+__device__ __forceinline__ void reciprocals(const double *r, double *inv) {
+    static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "N is a power of two");
+    const double pr = tree_product<N>(r);
+    double y = __builtin_amdgcn_rcp(pr);
+    const double e = __builtin_fma(-pr, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    tree_inverse<N>(r, y, inv);
 }
 
 __device__ __forceinline__ double mul_rn(double a, double b) {
@@ -75,6 +80,11 @@ __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, i
     // Fold the mass into the per-column and per-row offsets when that takes
     // fewer multiplies (CX + CY per star) than weighting every ray (CX * CY).
     constexpr bool FOLD = CX * CY > CX + CY;
+    // SHARE factors r^2 share one reciprocal: NS stars times RG neighbouring
+    // rays of a row (RG = 2 once more than 4 factors share it).
+    constexpr int NS = SHARE > 4 ? 4 : SHARE;
+    constexpr int RG = SHARE / NS;
+    static_assert(NS * RG == SHARE && CX % RG == 0, "SHARE = NS stars x RG rays");
     const int lx = threadIdx.x % kLanesX;
     const int ly = threadIdx.x / kLanesX;
     const int64_t tile_i = (tile % p.tiles_x) * (kLanesX * CX);
@@ -92,35 +102,35 @@ __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, i
 #pragma unroll
         for (int a = 0; a < CX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
 
-    const Star *__restrict__ st = p.stars;
+    const ConstStar *st = const_stars(p.stars);
     const int n = p.n_stars;
     int k = 0;
     // star groups are double-buffered: the next group's scalar loads are in
     // flight while the current group is computed (the index of the group
     // after the last stays on the last, so every load is in bounds)
-    double sx[SHARE], sy[SHARE], sm[SHARE];
-    if (n >= SHARE) {
+    double sx[NS], sy[NS], sm[NS];
+    if (n >= NS) {
 #pragma unroll
-        for (int s = 0; s < SHARE; ++s) {
+        for (int s = 0; s < NS; ++s) {
             sx[s] = st[s].x;
             sy[s] = st[s].y;
             sm[s] = st[s].m;
         }
     }
-    for (; k + SHARE <= n; k += SHARE) {
-        const int kn = (k + 2 * SHARE <= n) ? k + SHARE : k;
-        double nx[SHARE], ny[SHARE], nm[SHARE];
+    for (; k + NS <= n; k += NS) {
+        const int kn = (k + 2 * NS <= n) ? k + NS : k;
+        double nx[NS], ny[NS], nm[NS];
 #pragma unroll
-        for (int s = 0; s < SHARE; ++s) {
+        for (int s = 0; s < NS; ++s) {
             nx[s] = st[kn + s].x;
             ny[s] = st[kn + s].y;
             nm[s] = st[kn + s].m;
         }
         // per column: the x offset and (FOLD) the offset times the mass;
         // per row: the square of the y offset and the y offset (times the mass)
-        double ex[SHARE][CX], mex[SHARE][CX], ey2[SHARE][CY], mey[SHARE][CY];
+        double ex[NS][CX], mex[NS][CX], ey2[NS][CY], mey[NS][CY];
 #pragma unroll
-        for (int s = 0; s < SHARE; ++s) {
+        for (int s = 0; s < NS; ++s) {
 #pragma unroll
             for (int a = 0; a < CX; ++a) {
                 ex[s][a] = tx[a] - sx[s];
@@ -136,21 +146,28 @@ __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, i
 #pragma unroll
         for (int b = 0; b < CY; ++b) {
 #pragma unroll
-            for (int a = 0; a < CX; ++a) {
-                double r2[SHARE], inv[SHARE];
+            for (int a0 = 0; a0 < CX; a0 += RG) {
+                // RG neighbouring rays of the row and NS stars share one reciprocal
+                double r2[RG * NS], inv[RG * NS];
 #pragma unroll
-                for (int s = 0; s < SHARE; ++s) r2[s] = __builtin_fma(ex[s][a], ex[s][a], ey2[s][b]);
-                reciprocals<SHARE>(r2, inv);
+                for (int g = 0; g < RG; ++g)
 #pragma unroll
-                for (int s = 0; s < SHARE; ++s) {
-                    const double w = FOLD ? inv[s] : sm[s] * inv[s];
-                    ax[b][a] = __builtin_fma(w, mex[s][a], ax[b][a]);
-                    ay[b][a] = __builtin_fma(w, mey[s][b], ay[b][a]);
+                    for (int s = 0; s < NS; ++s)
+                        r2[g * NS + s] = __builtin_fma(ex[s][a0 + g], ex[s][a0 + g], ey2[s][b]);
+                reciprocals<RG * NS>(r2, inv);
+#pragma unroll
+                for (int g = 0; g < RG; ++g) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        const double w = FOLD ? inv[g * NS + s] : sm[s] * inv[g * NS + s];
+                        ax[b][a0 + g] = __builtin_fma(w, mex[s][a0 + g], ax[b][a0 + g]);
+                        ay[b][a0 + g] = __builtin_fma(w, mey[s][b], ay[b][a0 + g]);
+                    }
                 }
             }
         }
 #pragma unroll
-        for (int s = 0; s < SHARE; ++s) {
+        for (int s = 0; s < NS; ++s) {
             sx[s] = nx[s];
             sy[s] = ny[s];
             sm[s] = nm[s];
@@ -194,10 +211,10 @@ __global__ __launch_bounds__(kThreads) void batch_fp64_kernel(BatchArgs b) {
         if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.queue, 1ull);
         bin_shared_init(sh);
         __syncthreads();
-        const long long item = s_item;
-        if (item >= b.total_items) break;   // uniform: every wave leaves
-        const int set = find_set(b, item);
-        const BatchSet &bs = b.sets[set];
+        const long long item_all = s_item;
+        if (item_all >= b.total_items) break;   // every wave reads the same value and leaves
+        const int item = uniform((int)item_all);
+        const BatchSet bs = load_set(&b.sets[find_set(b, item)]);
         const int64_t t0 = (item - bs.first_item) * bs.tiles_per_item;
         const int64_t t1 = t0 + bs.tiles_per_item < bs.n_tiles ? t0 + bs.tiles_per_item : bs.n_tiles;
         for (int64_t t = t0; t < t1; ++t) {   // uniform trip count
@@ -240,14 +257,14 @@ hipError_t launch(const ShootParams &p, hipStream_t s) {
 #define RAYSH_FP64_SHAPES(X) \
     X(1, 4, 2)               \
     X(2, 2, 2)               \
-    X(2, 4, 1)               \
-    X(2, 4, 2)               \
     X(2, 4, 4)               \
+    X(2, 4, 8)               \
     X(4, 2, 4)               \
+    X(4, 2, 8)               \
     X(4, 4, 2)               \
     X(4, 4, 4)               \
-    X(2, 8, 2)               \
-    X(2, 8, 4)
+    X(4, 4, 8)               \
+    X(2, 8, 2)
 
 int fp64_shape_list(TileShape *out, int cap) {
     int n = 0;

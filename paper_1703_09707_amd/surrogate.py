@@ -336,11 +336,14 @@ def main(argv=None):
     res, pred = evaluate(net, std, train_data, test_data, noise_data)
     torch = _torch()
     x = torch.from_numpy(std(test_data.features)).cuda()
-    net.forward(x)
+    chunks = [x[i:i + net.max_batch].contiguous() for i in range(0, x.shape[0], net.max_batch)]
+    for c in chunks:
+        net.forward(c)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(20):
-        net.forward(x)
+        for c in chunks:
+            net.forward(c)
     torch.cuda.synchronize()
     t_pred = (time.perf_counter() - t2) / 20
     res.update({

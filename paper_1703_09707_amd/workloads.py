@@ -219,6 +219,23 @@ def precision_subtile(w: Workload, n: int = 2048) -> RayGrid:
     return w.rays.block((w.rays.nx - n) // 2, (w.rays.ny - n) // 2, n, n)
 
 
+def large_star_field(n_stars: int = 1 << 24, rays_per_side: int = 512, npix: int = 256,
+                     seed: int = BASE_SEED + 5) -> Workload:
+    """Many stars, few rays (the regime that Sec. 4 says needs the star sum
+    split across threads): n_stars Salpeter stars with kappa_star = 0.45,
+    kappa_c = 0, gamma = (0.3, 0); a rays_per_side^2 lattice over the
+    preimage of a 2 x 2 window around the centre; npix^2 map."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ks, kc, g1, g2 = 0.45, 0.0, 0.3, 0.0
+    m = salpeter_masses(n_stars, rng)
+    x, y, _ = star_field(m, ks, rng)
+    pix = centred_window(2.0, npix)
+    hx, hy = preimage_half_widths(kc + ks, g1, g2, 1.0, 1.0)
+    rays = centred_rays(hx, hy, rays_per_side, rays_per_side)
+    return Workload(f"large-star-field: N*={n_stars} Salpeter, {rays_per_side}^2 rays, {npix}^2 map",
+                    Lens(kc, g1, g2, x, y, m, ks), rays, pix, seed)
+
+
 def draw_batch_params(rng: np.random.Generator, n_sets: int, n_lo: int = 500,
                       n_hi: int = 50000, window: float = 10.0):
     """Rejection draw of (kappa, gamma, kappa_star/kappa) with

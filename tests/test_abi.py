@@ -35,7 +35,7 @@ def test_compiled_tile_lists():
     f64 = R.list_tiles("fp64")
     f32 = R.list_tiles("fp32_bulk")
     assert len(f64) >= 5 and len(f32) >= 5
-    assert all(t[3] == 0 and t[2] in (1, 2, 4) for t in f64)
+    assert all(t[3] == 0 and t[2] in (1, 2, 4, 8) for t in f64)
     assert all(t[2] == 0 and t[3] > 0 for t in f32)
     lib = R.load()
     assert lib.raysh_list_tiles(5, None, 0) == -R.EINVAL

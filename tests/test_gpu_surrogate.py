@@ -140,6 +140,7 @@ def test_network_beats_the_method_without_it(torch):
     net, std, hist = S.train(train, steps=2500, batch=256, lr=2e-3)
     res, _ = S.evaluate(net, std, train, test)
     x = torch.from_numpy(std(test.features)).cuda()
+    assert x.shape[0] <= net.max_batch
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(10):
