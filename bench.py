@@ -14,11 +14,12 @@ peak; the kernel's own time comes from HIP events recorded on the stream the
 kernel runs on.
 
 Also reported: the 64-set batch in one graph-captured persistent launch
-(against single launches), and the FP32-bulk misbinned fraction on the
-262144-star precision-study subtile.
+(against single launches), the FP32-bulk misbinned fraction on the
+262144-star precision-study subtile, and the split star sum on 4194304 stars
+x 256^2 rays (against one pass per ray).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
-                       [--no-batch] [--no-precision]
+                       [--no-batch] [--no-precision] [--no-split]
 """
 import argparse
 import json
@@ -43,6 +44,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-set batch timing")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision study")
+    ap.add_argument("--no-split", action="store_true", help="skip the many-stars/few-rays study")
     ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
     ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
     ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
@@ -136,6 +138,28 @@ def precision_section(torch, raysh, W):
     return {"workload": "precision-study subtile: 2048^2 rays x 262144 stars",
             "misbinned_fraction_fp32_bulk_vs_fp64": frac, "fp64_seconds": t64, "fp32_bulk_seconds": t32,
             "speedup": t64 / t32}
+
+
+def split_section(torch, raysh, W):
+    """Many stars, few rays: 4194304 stars x 256^2 rays.  One pass per ray
+    runs 16 workgroups; the split star sum spreads each ray's sum over
+    workgroups (automatic part count)."""
+    w = W.large_star_field(1 << 22, 256, 256)
+    out = {"workload": "large-star-field: 4194304 Salpeter stars x 256^2 rays, 256^2 map",
+           "interactions": w.interactions}
+    with raysh.Context(w.lens) as ctx:
+        for label, parts in (("split_auto", 0), ("one_pass", 1)):
+            ctx.set_star_split(parts)
+            counts = torch.zeros((w.pix.NY, w.pix.NX), dtype=torch.int32, device="cuda")
+            ctx.map(w.rays, w.pix, "fp64", counts=counts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.map(w.rays, w.pix, "fp64", counts=counts)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            out[label] = {"value": w.interactions / dt, "unit": "interactions/s", "seconds": dt}
+    out["speedup"] = out["one_pass"]["seconds"] / out["split_auto"]["seconds"]
+    return out
 
 
 def cpu_baseline(w, side):
@@ -237,6 +261,9 @@ def main():
     if not args.no_precision:
         print("# precision study", file=sys.stderr, flush=True)
         out["precision_study"] = precision_section(torch, raysh, W)
+    if not args.no_split:
+        print("# many stars, few rays (split star sum)", file=sys.stderr, flush=True)
+        out["split_star_sum"] = split_section(torch, raysh, W)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)

@@ -125,6 +125,22 @@ int64_t raysh_n_stars(const raysh_ctx *ctx);
  */
 int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int star_tile);
 
+/*
+ * raysh_set_star_split: split each ray's FP64 star sum over `parts`
+ * contiguous star ranges computed by separate workgroups (for many stars
+ * and few rays, where one pass over all stars per ray cannot fill the GPU;
+ * Sec. 4 of the paper suggests splitting the bending-angle sum between
+ * threads).  The partial sums (FP64, one pair per ray and part, in a
+ * context-owned workspace of parts * nx * ny * 16 bytes that grows on
+ * demand) are added in part order after the macro term; results differ
+ * from one pass only by rounding.  parts = 1 (the default) is one pass;
+ * parts = 0 picks a count per call from the number of ray tiles and stars
+ * (at least 64 stars per part, workspace at most 2 GiB).  Applies to
+ * RAYSH_FP64 calls of raysh_shoot and raysh_map.  EINVAL outside [0, 65536];
+ * ENOMEM at call time if the workspace cannot be allocated.
+ */
+int raysh_set_star_split(raysh_ctx *ctx, int parts);
+
 /* The launch shapes compiled for `precision`: writes up to `cap` shapes as
  * 4 ints each (cx, cy, share, star_tile) into `shapes` (may be NULL when
  * cap is 0) and returns how many exist, or -RAYSH_EINVAL for an unknown

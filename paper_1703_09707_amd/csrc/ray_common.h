@@ -164,6 +164,17 @@ __device__ __forceinline__ const ConstStar *const_stars(const Star *p) {
 // A value every lane holds alike, moved to a scalar register.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ const Star *uniform_ptr(const Star *p) {
+    return (const Star *)(uintptr_t)uniform64((int64_t)(uintptr_t)p);
+}
+
 // Set owning queue item `item` (binary search over first_item; uniform).
 __device__ __forceinline__ int find_set(const BatchArgs &b, int item) {
     int lo = 0, hi = b.n_sets - 1;
@@ -175,20 +186,16 @@ __device__ __forceinline__ int find_set(const BatchArgs &b, int item) {
     return uniform(lo);
 }
 
-// The set's parameters, copied word by word into scalar registers.
-__device__ __forceinline__ BatchSet load_set(const BatchSet *src) {
-    static_assert(sizeof(BatchSet) % 4 == 0, "BatchSet is a whole number of words");
-    BatchSet out;
-    const char *s = reinterpret_cast<const char *>(src);
-    char *d = reinterpret_cast<char *>(&out);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(BatchSet) / 4); ++i) {
+// Copy a set's parameters to LDS, one word per thread (the caller then
+// waits at a barrier).
+__device__ __forceinline__ void copy_set_to_lds(const BatchSet *src, BatchSet *dst) {
+    static_assert(sizeof(BatchSet) % 4 == 0 && sizeof(BatchSet) / 4 <= kThreads,
+                  "one word of BatchSet per thread");
+    if (threadIdx.x < sizeof(BatchSet) / 4) {
         int w;
-        __builtin_memcpy(&w, s + 4 * i, 4);
-        w = uniform(w);
-        __builtin_memcpy(d + 4 * i, &w, 4);
+        __builtin_memcpy(&w, reinterpret_cast<const char *>(src) + 4 * threadIdx.x, 4);
+        __builtin_memcpy(reinterpret_cast<char *>(dst) + 4 * threadIdx.x, &w, 4);
     }
-    return out;
 }
 
 }  // namespace raysh

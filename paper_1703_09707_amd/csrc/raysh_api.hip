@@ -1,6 +1,7 @@
 // Host side of the raysh C ABI: argument validation, contexts, star upload
 // and kernel dispatch.  The operation itself is Eq. (1)-(3) and Algorithm 1
 // of arXiv:1703.09707 (see include/raysh.h for the conventions).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -21,9 +22,54 @@ thread_local char g_err[512] = "";
 constexpr int64_t kMaxRays = std::numeric_limits<int32_t>::max();
 constexpr int64_t kMaxIndex = int64_t(1) << 53;
 
-hipError_t launch(const raysh_ctx *c, const ShootParams &p, int precision) {
-    if (precision == RAYSH_FP64) return raysh::launch_shoot_fp64(p, c->shape[0], c->stream);
-    return raysh::launch_shoot_fp32(p, c->shape[1], c->stream);
+constexpr size_t kMaxSplitBytes = size_t(2) << 30;   // automatic split-K workspace cap
+constexpr int kMinStarsPerPart = 64;
+
+// Parts of the FP64 star sum for this call (1 = one pass).
+int split_parts(const raysh_ctx *c, const ShootParams &p) {
+    if (c->star_parts >= 1) return c->star_parts;   // as set (1 = one pass)
+    // automatic: enough (tile, part) workgroups to fill the GPU several times
+    if (c->n_stars < 2 * kMinStarsPerPart) return 1;
+    const int64_t n_rays = p.nx * p.ny;
+    const TileShape &t = c->shape[0];
+    const int64_t tiles = ((p.nx + raysh::tile_width(t) - 1) / raysh::tile_width(t)) *
+                          ((p.ny + raysh::tile_height(t) - 1) / raysh::tile_height(t));
+    const int64_t want_blocks = (int64_t)std::max(c->n_cu, 1) * 8;   // several waves of workgroups
+    int64_t parts = (want_blocks + tiles - 1) / tiles;
+    parts = std::min<int64_t>(parts, c->n_stars / kMinStarsPerPart);
+    parts = std::min<int64_t>(parts, (int64_t)(kMaxSplitBytes / (16 * (size_t)n_rays)));
+    return (int)std::max<int64_t>(parts, 1);
+}
+
+int launch(raysh_ctx *c, const ShootParams &p, int precision, const char *what) {
+    hipError_t e;
+    if (precision == RAYSH_FP64) {
+        const int parts = split_parts(c, p);
+        if (parts > 1) {
+            const size_t need = (size_t)parts * (size_t)(p.nx * p.ny) * sizeof(double2);
+            if (need > c->partial_bytes) {
+                e = hipStreamSynchronize(c->stream);   // the old workspace may still be read
+                if (e != hipSuccess) return hip_error(e, what);
+                if (c->d_partial) (void)hipFree(c->d_partial);
+                c->d_partial = nullptr;
+                c->partial_bytes = 0;
+                e = hipMalloc(&c->d_partial, need);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    c->d_partial = nullptr;
+                    return set_error(RAYSH_ENOMEM, "%s: split-K workspace of %zu bytes", what, need);
+                }
+                c->partial_bytes = need;
+            }
+            e = raysh::launch_split_fp64(p, c->shape[0], parts, c->d_partial, c->stream);
+        } else {
+            e = raysh::launch_shoot_fp64(p, c->shape[0], c->stream);
+        }
+    } else {
+        e = raysh::launch_shoot_fp32(p, c->shape[1], c->stream);
+    }
+    if (e != hipSuccess) return hip_error(e, what);
+    return RAYSH_OK;
 }
 
 }  // namespace
@@ -171,6 +217,10 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
     c->k11 = lens->kappa_c + lens->gamma1;
     c->k12 = lens->gamma2;
     c->k22 = lens->kappa_c - lens->gamma1;
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        (void)hipGetLastError();
+        c->n_cu = 1;
+    }
 
     std::vector<Star> host((size_t)(n > 0 ? n : 1), Star{0, 0, 0, 0});
     for (int64_t k = 0; k < n; ++k) host[(size_t)k] = Star{lens->x[k], lens->y[k], lens->m[k], 0.0};
@@ -193,6 +243,13 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
         return code;
     }
     *out = c;
+    return set_ok();
+}
+
+int raysh_set_star_split(raysh_ctx *ctx, int parts) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    if (parts < 0 || parts > 65536) return set_error(RAYSH_EINVAL, "star split %d outside [0, 65536]", parts);
+    ctx->star_parts = parts;
     return set_ok();
 }
 
@@ -274,8 +331,7 @@ int raysh_shoot(raysh_ctx *ctx, const raysh_rays *rays, int precision, double *b
     p.beta_x = beta_x;
     p.beta_y = beta_y;
     p.bin = bin;
-    hipError_t e = launch(ctx, p, precision);
-    if (e != hipSuccess) return hip_error(e, "raysh_shoot launch");
+    if (int r = launch(ctx, p, precision, "raysh_shoot")) return r;
     return set_ok();
 }
 
@@ -304,8 +360,7 @@ int raysh_map(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix, i
         e = raysh::launch_zero_u64(ctx->d_counter, 1, ctx->stream);
         if (e != hipSuccess) return hip_error(e, "raysh_map counter reset");
     }
-    e = launch(ctx, p, precision);
-    if (e != hipSuccess) return hip_error(e, "raysh_map launch");
+    if (int r = launch(ctx, p, precision, "raysh_map")) return r;
     if (n_binned) {
         e = hipMemcpyAsync(ctx->h_counter, ctx->d_counter, sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, ctx->stream);
@@ -333,6 +388,7 @@ int raysh_free(raysh_ctx *ctx) {
         if (hipStreamSynchronize(ctx->stream) != hipSuccess) code = RAYSH_EDEVICE;
         if (ctx->d_stars) (void)hipFree(ctx->d_stars);
         if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+        if (ctx->d_partial) (void)hipFree(ctx->d_partial);
         if (ctx->h_counter) (void)hipHostFree(ctx->h_counter);
     }
     delete ctx;

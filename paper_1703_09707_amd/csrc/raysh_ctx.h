@@ -15,6 +15,10 @@ struct raysh_ctx {
     unsigned long long *h_counter = nullptr;   // pinned
     // default launch shapes: the fastest on MI355X for the 16384-star workload
     raysh::TileShape shape[2] = {{4, 4, 8, 0}, {4, 4, 0, 128}};
+    int star_parts = 1;                    // FP64 split of each ray's star sum (0 = automatic)
+    double2 *d_partial = nullptr;          // split-K workspace
+    size_t partial_bytes = 0;
+    int n_cu = 0;
 };
 
 // Error reporting: store a message for raysh_last_error and return code.

@@ -75,6 +75,10 @@ int tile_width(const TileShape &shape);   // rays per tile along x (16 * cx)
 int tile_height(const TileShape &shape);  // rays per tile along y (16 * cy)
 
 hipError_t launch_batch_fp64(const BatchArgs &b, const TileShape &shape, int blocks, hipStream_t s);
+// Split-K FP64: partial star sums over `parts` star ranges into `partial`
+// (parts * nx * ny FP64 pairs), then the finishing pass.
+hipError_t launch_split_fp64(const ShootParams &p, const TileShape &shape, int parts, double2 *partial,
+                             hipStream_t s);
 hipError_t launch_batch_fp32(const BatchArgs &b, const TileShape &shape, int blocks, hipStream_t s);
 int batch_fp64_blocks_per_cu(const TileShape &shape);
 int batch_fp32_blocks_per_cu(const TileShape &shape);

@@ -56,8 +56,8 @@ __device__ __forceinline__ void fp32_tile(const ShootParams &p, BinShared &sh, f
 #pragma unroll
         for (int a = 0; a < CX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
 
-    const Star *__restrict__ st = p.stars;
-    const int n = p.n_stars;
+    const Star *__restrict__ st = uniform_ptr(p.stars);
+    const int n = uniform(p.n_stars);
     for (int base = 0; base < n; base += S) {
         const int cnt = (n - base < S) ? (n - base) : S;
         if ((int)threadIdx.x < cnt) {
@@ -125,6 +125,7 @@ template <int CX, int CY, int S>
 __global__ __launch_bounds__(kThreads) void batch_fp32_kernel(BatchArgs b) {
     __shared__ BinShared sh;
     __shared__ float4 stage[S];
+    __shared__ BatchSet s_set;
     __shared__ long long s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.queue, 1ull);
@@ -133,15 +134,18 @@ __global__ __launch_bounds__(kThreads) void batch_fp32_kernel(BatchArgs b) {
         const long long item_all = s_item;
         if (item_all >= b.total_items) break;   // every wave reads the same value and leaves
         const int item = uniform((int)item_all);
-        const BatchSet bs = load_set(&b.sets[find_set(b, item)]);
-        const int64_t t0 = (item - bs.first_item) * bs.tiles_per_item;
-        const int64_t t1 = t0 + bs.tiles_per_item < bs.n_tiles ? t0 + bs.tiles_per_item : bs.n_tiles;
+        copy_set_to_lds(&b.sets[find_set(b, item)], &s_set);
+        __syncthreads();
+        const int64_t per = uniform(s_set.tiles_per_item);
+        const int64_t t0 = (item - uniform64(s_set.first_item)) * per;
+        const int64_t n_tiles = uniform64(s_set.n_tiles);
+        const int64_t t1 = t0 + per < n_tiles ? t0 + per : n_tiles;
         for (int64_t t = t0; t < t1; ++t) {   // uniform trip count
-            fp32_tile<CX, CY, S>(bs.p, sh, stage, t);
+            fp32_tile<CX, CY, S>(s_set.p, sh, stage, t);
             __syncthreads();   // red, the window and the stage are reused
             bin_shared_init(sh);
         }
-        __syncthreads();   // s_item is rewritten
+        __syncthreads();   // s_item and s_set are rewritten
     }
 }
 

@@ -73,10 +73,12 @@ __device__ __forceinline__ double mul_rn(double a, double b) {
     return a * b;
 }
 
-// One ray tile (all of Algorithm 1 for its rays).  sh.red must be zero on
-// entry; every thread of the workgroup must call it.
+// The second term of Eq. (3) for stars [k0, k1) of a lane's CX x CY rays,
+// added to (ax, ay) in star index order.
 template <int CX, int CY, int SHARE>
-__device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, int64_t tile) {
+__device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, const double (&tx)[CX],
+                                         const double (&ty)[CY], double (&ax)[CY][CX],
+                                         double (&ay)[CY][CX]) {
     // Fold the mass into the per-column and per-row offsets when that takes
     // fewer multiplies (CX + CY per star) than weighting every ray (CX * CY).
     constexpr bool FOLD = CX * CY > CX + CY;
@@ -85,40 +87,21 @@ __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, i
     constexpr int NS = SHARE > 4 ? 4 : SHARE;
     constexpr int RG = SHARE / NS;
     static_assert(NS * RG == SHARE && CX % RG == 0, "SHARE = NS stars x RG rays");
-    const int lx = threadIdx.x % kLanesX;
-    const int ly = threadIdx.x / kLanesX;
-    const int64_t tile_i = (tile % p.tiles_x) * (kLanesX * CX);
-    const int64_t tile_j = (tile / p.tiles_x) * (kLanesY * CY);
-
-    double tx[CX], ty[CY];
-#pragma unroll
-    for (int a = 0; a < CX; ++a) tx[a] = image_angle(p.x0, p.i0 + tile_i + lx + kLanesX * a, p.dx);
-#pragma unroll
-    for (int b = 0; b < CY; ++b) ty[b] = image_angle(p.y0, p.j0 + tile_j + ly + kLanesY * b, p.dy);
-
-    double ax[CY][CX], ay[CY][CX];
-#pragma unroll
-    for (int b = 0; b < CY; ++b)
-#pragma unroll
-        for (int a = 0; a < CX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
-
-    const ConstStar *st = const_stars(p.stars);
-    const int n = p.n_stars;
-    int k = 0;
+    int k = k0;
     // star groups are double-buffered: the next group's scalar loads are in
     // flight while the current group is computed (the index of the group
     // after the last stays on the last, so every load is in bounds)
     double sx[NS], sy[NS], sm[NS];
-    if (n >= NS) {
+    if (k + NS <= k1) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            sx[s] = st[s].x;
-            sy[s] = st[s].y;
-            sm[s] = st[s].m;
+            sx[s] = st[k + s].x;
+            sy[s] = st[k + s].y;
+            sm[s] = st[k + s].m;
         }
     }
-    for (; k + NS <= n; k += NS) {
-        const int kn = (k + 2 * NS <= n) ? k + NS : k;
+    for (; k + NS <= k1; k += NS) {
+        const int kn = (k + 2 * NS <= k1) ? k + NS : k;
         double nx[NS], ny[NS], nm[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -173,24 +156,55 @@ __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, i
             sm[s] = nm[s];
         }
     }
-    for (; k < n; ++k) {   // remaining stars, one at a time, still in index order
-        const double sx = st[k].x, sy = st[k].y, sm = st[k].m;
+    for (; k < k1; ++k) {   // remaining stars, one at a time, still in index order
+        const double sx1 = st[k].x, sy1 = st[k].y, sm1 = st[k].m;
 #pragma unroll
         for (int b = 0; b < CY; ++b) {
-            const double ey = ty[b] - sy;
+            const double ey = ty[b] - sy1;
             const double ey2 = mul_rn(ey, ey);
 #pragma unroll
             for (int a = 0; a < CX; ++a) {
-                const double ex = tx[a] - sx;
+                const double ex = tx[a] - sx1;
                 double r2[1] = {__builtin_fma(ex, ex, ey2)}, inv[1];
                 reciprocals<1>(r2, inv);
-                const double w = sm * inv[0];
+                const double w = sm1 * inv[0];
                 ax[b][a] = __builtin_fma(w, ex, ax[b][a]);
                 ay[b][a] = __builtin_fma(w, ey, ay[b][a]);
             }
         }
     }
+}
 
+// Image angles of a lane's CX columns and CY rows in ray tile `tile`.
+template <int CX, int CY>
+__device__ __forceinline__ void tile_rays(const ShootParams &p, int64_t tile, double (&tx)[CX],
+                                          double (&ty)[CY], int64_t &tile_i, int64_t &tile_j, int &lx,
+                                          int &ly) {
+    lx = threadIdx.x % kLanesX;
+    ly = threadIdx.x / kLanesX;
+    const int64_t tiles_x = uniform(p.tiles_x);
+    tile_i = (tile % tiles_x) * (kLanesX * CX);
+    tile_j = (tile / tiles_x) * (kLanesY * CY);
+#pragma unroll
+    for (int a = 0; a < CX; ++a) tx[a] = image_angle(p.x0, p.i0 + tile_i + lx + kLanesX * a, p.dx);
+#pragma unroll
+    for (int b = 0; b < CY; ++b) ty[b] = image_angle(p.y0, p.j0 + tile_j + ly + kLanesY * b, p.dy);
+}
+
+// One ray tile (all of Algorithm 1 for its rays).  sh.red must be zero on
+// entry; every thread of the workgroup must call it.
+template <int CX, int CY, int SHARE>
+__device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, int64_t tile) {
+    double tx[CX], ty[CY];
+    int64_t tile_i, tile_j;
+    int lx, ly;
+    tile_rays<CX, CY>(p, tile, tx, ty, tile_i, tile_j, lx, ly);
+    double ax[CY][CX], ay[CY][CX];
+#pragma unroll
+    for (int b = 0; b < CY; ++b)
+#pragma unroll
+        for (int a = 0; a < CX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
+    star_sum<CX, CY, SHARE>(const_stars(uniform_ptr(p.stars)), 0, uniform(p.n_stars), tx, ty, ax, ay);
     finish_tile<CX, CY>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
 }
 
@@ -201,11 +215,16 @@ __global__ __launch_bounds__(kThreads) void shoot_fp64_kernel(ShootParams p) {
     fp64_tile<CX, CY, SHARE>(p, sh, blockIdx.x);
 }
 
-// Persistent form: workgroups take (set, tile) items from a device queue
-// until it is empty.
+// Persistent form: workgroups take items (runs of ray tiles of one set)
+// from a device queue until it is empty.  The item's set is staged in LDS;
+// the values the star loop needs are moved to scalar registers.  At least
+// two waves per SIMD are requested: the queue loop keeps a few more values
+// live than one tile does, and the compiler would otherwise give up the
+// second wave for them.
 template <int CX, int CY, int SHARE>
-__global__ __launch_bounds__(kThreads) void batch_fp64_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kThreads, 2) void batch_fp64_kernel(BatchArgs b) {
     __shared__ BinShared sh;
+    __shared__ BatchSet s_set;
     __shared__ long long s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.queue, 1ull);
@@ -214,16 +233,87 @@ __global__ __launch_bounds__(kThreads) void batch_fp64_kernel(BatchArgs b) {
         const long long item_all = s_item;
         if (item_all >= b.total_items) break;   // every wave reads the same value and leaves
         const int item = uniform((int)item_all);
-        const BatchSet bs = load_set(&b.sets[find_set(b, item)]);
-        const int64_t t0 = (item - bs.first_item) * bs.tiles_per_item;
-        const int64_t t1 = t0 + bs.tiles_per_item < bs.n_tiles ? t0 + bs.tiles_per_item : bs.n_tiles;
+        copy_set_to_lds(&b.sets[find_set(b, item)], &s_set);
+        __syncthreads();
+        const int64_t per = uniform(s_set.tiles_per_item);
+        const int64_t t0 = (item - uniform64(s_set.first_item)) * per;
+        const int64_t n_tiles = uniform64(s_set.n_tiles);
+        const int64_t t1 = t0 + per < n_tiles ? t0 + per : n_tiles;
         for (int64_t t = t0; t < t1; ++t) {   // uniform trip count
-            fp64_tile<CX, CY, SHARE>(bs.p, sh, t);
+            fp64_tile<CX, CY, SHARE>(s_set.p, sh, t);
             __syncthreads();   // red and the window are reused
             bin_shared_init(sh);
         }
-        __syncthreads();   // s_item is rewritten
+        __syncthreads();   // s_item and s_set are rewritten
     }
+}
+
+// Split-K form for many stars and few rays (the star sum of one ray split
+// across workgroups): block (part, tile) adds stars [part*chunk, ...) for
+// the tile's rays into partial[part][ray] (FP64 pairs, ray = j*nx + i of
+// the block).  Blocks are numbered part-major, so blocks running together
+// share their stars in the caches.
+template <int CX, int CY, int SHARE>
+__global__ __launch_bounds__(kThreads) void partial_fp64_kernel(ShootParams p, int64_t n_tiles, int chunk,
+                                                                double2 *__restrict__ partial) {
+    const int part = (int)(blockIdx.x / n_tiles);
+    const int64_t tile = blockIdx.x % n_tiles;
+    double tx[CX], ty[CY];
+    int64_t tile_i, tile_j;
+    int lx, ly;
+    tile_rays<CX, CY>(p, tile, tx, ty, tile_i, tile_j, lx, ly);
+    double ax[CY][CX], ay[CY][CX];
+#pragma unroll
+    for (int b = 0; b < CY; ++b)
+#pragma unroll
+        for (int a = 0; a < CX; ++a) ax[b][a] = ay[b][a] = 0.0;
+    const int64_t n = uniform(p.n_stars);
+    const int64_t first = (int64_t)part * chunk;
+    const int k0 = (int)(first < n ? first : n);
+    const int k1 = (int)(k0 + (int64_t)chunk < n ? k0 + (int64_t)chunk : n);
+    star_sum<CX, CY, SHARE>(const_stars(uniform_ptr(p.stars)), k0, k1, tx, ty, ax, ay);
+    const int64_t n_rays = p.nx * p.ny;
+#pragma unroll
+    for (int b = 0; b < CY; ++b) {
+#pragma unroll
+        for (int a = 0; a < CX; ++a) {
+            const int64_t i = tile_i + lx + kLanesX * a;
+            const int64_t j = tile_j + ly + kLanesY * b;
+            if (i < p.nx && j < p.ny) partial[part * n_rays + j * p.nx + i] = make_double2(ax[b][a], ay[b][a]);
+        }
+    }
+}
+
+// Finish of split-K: alpha = K theta, then the parts' partial sums in part
+// order, then beta, pixel and counts as in one pass.
+template <int CX, int CY>
+__global__ __launch_bounds__(kThreads) void finish_fp64_kernel(ShootParams p, int parts,
+                                                               const double2 *__restrict__ partial) {
+    __shared__ BinShared sh;
+    bin_shared_init(sh);
+    double tx[CX], ty[CY];
+    int64_t tile_i, tile_j;
+    int lx, ly;
+    tile_rays<CX, CY>(p, blockIdx.x, tx, ty, tile_i, tile_j, lx, ly);
+    const int64_t n_rays = p.nx * p.ny;
+    double ax[CY][CX], ay[CY][CX];
+#pragma unroll
+    for (int b = 0; b < CY; ++b) {
+#pragma unroll
+        for (int a = 0; a < CX; ++a) {
+            macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
+            const int64_t i = tile_i + lx + kLanesX * a;
+            const int64_t j = tile_j + ly + kLanesY * b;
+            if (i < p.nx && j < p.ny) {
+                for (int q = 0; q < parts; ++q) {
+                    const double2 v = partial[q * n_rays + j * p.nx + i];
+                    ax[b][a] += v.x;
+                    ay[b][a] += v.y;
+                }
+            }
+        }
+    }
+    finish_tile<CX, CY>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
 }
 
 template <int CX, int CY, int SHARE>
@@ -249,6 +339,24 @@ hipError_t launch(const ShootParams &p, hipStream_t s) {
     const int64_t blocks = (int64_t)q.tiles_x * tiles_y;
     hipLaunchKernelGGL((shoot_fp64_kernel<CX, CY, SHARE>), dim3((unsigned)blocks), dim3(kThreads),
                        0, s, q);
+    return hipGetLastError();
+}
+
+template <int CX, int CY, int SHARE>
+hipError_t launch_split(const ShootParams &p, int parts, double2 *partial, hipStream_t s) {
+    ShootParams q = p;
+    q.tiles_x = (int32_t)((p.nx + kLanesX * CX - 1) / (kLanesX * CX));
+    const int64_t tiles_y = (p.ny + kLanesY * CY - 1) / (kLanesY * CY);
+    const int64_t n_tiles = (int64_t)q.tiles_x * tiles_y;
+    constexpr int NS = SHARE > 4 ? 4 : SHARE;
+    int chunk = (int)((p.n_stars + parts - 1) / parts);
+    chunk = (chunk + NS - 1) / NS * NS;
+    hipLaunchKernelGGL((partial_fp64_kernel<CX, CY, SHARE>), dim3((unsigned)(n_tiles * parts)), dim3(kThreads),
+                       0, s, q, n_tiles, chunk, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((finish_fp64_kernel<CX, CY>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, q, parts,
+                       (const double2 *)partial);
     return hipGetLastError();
 }
 
@@ -287,6 +395,15 @@ bool fp64_shape_supported(const TileShape &t) {
 hipError_t launch_shoot_fp64(const ShootParams &p, const TileShape &t, hipStream_t s) {
 #define RAYSH_CASE(CX, CY, S) \
     if (t.cx == CX && t.cy == CY && t.share == S) return launch<CX, CY, S>(p, s);
+    RAYSH_FP64_SHAPES(RAYSH_CASE)
+#undef RAYSH_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_split_fp64(const ShootParams &p, const TileShape &t, int parts, double2 *partial,
+                             hipStream_t s) {
+#define RAYSH_CASE(CX, CY, S) \
+    if (t.cx == CX && t.cy == CY && t.share == S) return launch_split<CX, CY, S>(p, parts, partial, s);
     RAYSH_FP64_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
     return hipErrorInvalidValue;

@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": FP64, "fp32_bulk": FP32_BULK, FP64: FP64, FP32_BULK: FP32_
 OK, EINVAL, EOVERFLOW, ENOMEM, EDEVICE = 0, 1, 2, 3, 4
 _CODES = {EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"}
 
-EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", "raysh_list_tiles",
+EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", "raysh_set_star_split",
+           "raysh_list_tiles",
            "raysh_get_tile", "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch",
            "raysh_histogram_workspace", "raysh_log_mag_histogram", "raysh_mlp_create",
            "raysh_mlp_n_params", "raysh_mlp_get_params", "raysh_mlp_forward", "raysh_mlp_gradient",
@@ -81,6 +82,8 @@ def load():
     lib.raysh_n_stars.restype = ctypes.c_int64
     lib.raysh_set_tile.argtypes = [P, I, I, I, I, I]
     lib.raysh_get_tile.argtypes = [P, I] + [ctypes.POINTER(I)] * 4
+    lib.raysh_set_star_split.argtypes = [P, I]
+    lib.raysh_set_star_split.restype = I
     lib.raysh_list_tiles.argtypes = [I, ctypes.POINTER(ctypes.c_int32), I]
     lib.raysh_list_tiles.restype = I
     lib.raysh_histogram_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32]
@@ -192,6 +195,10 @@ class Context:
 
     def set_tile(self, precision, cx, cy, share=0, star_tile=0):
         check(load().raysh_set_tile(self.handle, PRECISIONS[precision], cx, cy, share, star_tile))
+
+    def set_star_split(self, parts):
+        """raysh_set_star_split: 1 = one pass, 0 = automatic, n = n parts."""
+        check(load().raysh_set_star_split(self.handle, int(parts)))
 
     def get_tile(self, precision):
         v = [ctypes.c_int() for _ in range(4)]

@@ -23,6 +23,9 @@ KERNEL_SOURCES = {
     "shoot_fp32_kernel": ["csrc/shoot_fp32.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "batch_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "batch_fp32_kernel": ["csrc/shoot_fp32.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+    "partial_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+    "finish_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+    "expansion_fp64_kernel": ["csrc/shoot_expansion.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
 }
 
 
@@ -52,6 +55,17 @@ def counter_values(db, name_like):
     for name, counter, value in _rows(db, "select name, counter_name, counter_value from pmc_events "
                                           "where name like ?", (f"%{name_like}%",)):
         out.setdefault(counter, []).append(value)
+    return out
+
+
+def dispatch_durations_us(db, name_like, grid=None):
+    """Durations (us) of the kernel's dispatches, optionally only those of
+    one grid size (threads)."""
+    sql = "select duration, grid_x * grid_y * grid_z from kernels where name like ?"
+    out = []
+    for dur, g in _rows(db, sql, (f"%{name_like}%",)):
+        if grid is None or g == grid:
+            out.append(dur / 1000.0)
     return out
 
 
@@ -86,6 +100,8 @@ def main(argv=None):
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="")
     ap.add_argument("--flop-per-launch", type=float, default=None)
+    ap.add_argument("--grid", type=int, default=None,
+                    help="only dispatches of this grid size (threads) give the kernel's time")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
@@ -99,6 +115,10 @@ def main(argv=None):
         if a.kernel in name and k_avg is None:
             k_avg = avg
     lines.append("")
+    durs = dispatch_durations_us(a.stats, a.kernel, a.grid)
+    if durs:
+        k_avg = sum(durs) / len(durs)
+        lines.append(f"dispatches: {len(durs)}" + (f" (grid {a.grid} threads)" if a.grid else ""))
     lines.append(f"avg_us: {k_avg}")
     expected_kib = a.copy_mib * 1024.0
     traffic = 0.0

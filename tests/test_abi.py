@@ -151,6 +151,7 @@ def test_other_argument_errors(lib):
     assert lib.raysh_autotune(None, r, p, 0, None, None, None, None, None) == R.EINVAL
     assert "ctx" in _err(lib)
     assert lib.raysh_sync(None) == R.EINVAL
+    assert lib.raysh_set_star_split(None, 2) == R.EINVAL
     assert lib.raysh_free(None) == R.OK
     assert lib.raysh_n_stars(None) == 0
 

@@ -415,3 +415,68 @@ def test_maximum_sizes(torch):
     bad = R.Rays(0.0, 0.0, 1.0, 1.0, 46341, 46341, 0, 0)   # 2147488281 rays > 2^31 - 1
     lib = R.load()
     assert lib.raysh_shoot(None, bad, 0, None, None, None, None) == R.EOVERFLOW
+
+
+# ----------------------------------------------------------------- split star sum (many stars, few rays)
+@pytest.mark.parametrize("parts", [2, 3, 7, 40])
+def test_star_split_matches_oracle(torch, small, small_oracle, parts):
+    """Each ray's star sum split over `parts` star ranges (40 > 100/4 groups:
+    some ranges are empty) still matches the oracle ray by ray."""
+    bx, by, b, counts, n, s = small_oracle
+    with R.Context(small.lens) as ctx:
+        ctx.set_star_split(parts)
+        gx, gy, gb = ctx.shoot(small.rays, "fp64", small.pix)
+        assert np.all(np.abs(_np(gx) - bx) <= BETA_TOL * s)
+        assert np.all(np.abs(_np(gy) - by) <= BETA_TOL * s)
+        assert np.count_nonzero(_np(gb) != b) <= MISBIN_FP64 * b.size
+        m, nb = ctx.map(small.rays, small.pix, "fp64", n_binned=True)
+        assert 0.5 * (np.abs(_np(m) - counts).sum() + abs(nb - n)) <= MISBIN_FP64 * b.size
+        # band additivity holds exactly at a fixed part count
+        acc = torch.zeros_like(m)
+        for j0, ny in ((0, 400), (400, 600)):
+            ctx.map(small.rays.block(0, j0, 1000, ny), small.pix, "fp64", counts=acc)
+        assert torch.equal(acc, m)
+
+
+def test_star_split_edge_cases(torch):
+    """Star counts that are not a multiple of the group size, a single star,
+    no stars, and ragged blocks, with splits."""
+    rng = np.random.default_rng(8)
+    pix = (-2.0, -2.0, 4 / 64, 4 / 64, 64, 64)
+    rays = (-3.0, -2.5, 6 / 77, 5 / 53, 77, 53, 0, 0)
+    for n_st in (0, 1, 5, 131):
+        xs, ys = rng.uniform(-2, 2, n_st), rng.uniform(-2, 2, n_st)
+        ms = rng.uniform(0.1, 1, n_st)
+        lens = (0.1, 0.2, -0.05, xs, ys, ms)
+        ox, oy, ob = ora.shoot(lens, rays, pix)
+        s = ora.error_scale_block(lens, rays)
+        with R.Context(lens) as ctx:
+            for parts in (0, 2, 9):
+                ctx.set_star_split(parts)
+                gx, gy, gb = ctx.shoot(rays, "fp64", pix)
+                assert np.all(np.abs(_np(gx) - ox) <= BETA_TOL * s), (n_st, parts)
+                assert np.all(np.abs(_np(gy) - oy) <= BETA_TOL * s), (n_st, parts)
+                assert np.count_nonzero(_np(gb) != ob) == 0, (n_st, parts)
+        with pytest.raises(R.RayshError):
+            R.Context(lens).set_star_split(-1)
+
+
+def test_large_star_field_split(torch):
+    """4194304 stars, 256^2 rays: the automatic split fills the GPU; sampled
+    rays match the oracle; the map equals the histogram of the bins."""
+    w = W.large_star_field(1 << 22, 256, 256)
+    rng = np.random.default_rng(9)
+    ii, jj = _sample(rng, w.rays.nx, w.rays.ny, 12)
+    ox, oy, ob = ora.shoot_list(w.lens.as_tuple(), w.rays.as_tuple(), w.pix.as_tuple(), ii, jj)
+    tx, ty = ora.image_angles(w.rays.as_tuple())
+    s = np.array([ora.error_scale(w.lens.as_tuple(), tx[i], ty[j])[0] for i, j in zip(ii, jj)])
+    with R.Context(w.lens) as ctx:
+        ctx.set_star_split(0)
+        gx, gy, gb = ctx.shoot(w.rays, "fp64", w.pix)
+        m = ctx.map(w.rays, w.pix, "fp64")
+        hist = torch.bincount(gb[gb >= 0].long(), minlength=w.pix.NX * w.pix.NY)
+        assert torch.equal(hist.to(torch.int32).view(w.pix.NY, w.pix.NX), m)
+        jt, it = torch.as_tensor(jj, device="cuda"), torch.as_tensor(ii, device="cuda")
+        assert np.count_nonzero(_np(gb[jt, it]) != ob) == 0
+        assert np.all(np.abs(_np(gx[jt, it]) - ox) <= BETA_TOL * s)
+        assert np.all(np.abs(_np(gy[jt, it]) - oy) <= BETA_TOL * s)
