@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-set batch timing")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision study")
     ap.add_argument("--no-split", action="store_true", help="skip the many-stars/few-rays study")
+    ap.add_argument("--no-expansion", action="store_true", help="skip the far-field expansion study")
     ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
     ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
     ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
@@ -162,6 +163,44 @@ def split_section(torch, raysh, W):
     return out
 
 
+def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup):
+    """FP64 with the far field of each ray tile as a local expansion, on the
+    large configuration (time per map against the one-pass FP64 map, and the
+    fraction of rays binned differently), and on the central 2048^2 rays of
+    the 262144-star precision-study lattice."""
+    out = {"workload": w.name, "interactions_equivalent": w.interactions}
+    with raysh.Context(w.lens) as ctx:
+        counts = torch.zeros((w.pix.NY, w.pix.NX), dtype=torch.int32, device="cuda")
+        wall, kms = time_steps(torch, ctx, w, "fp64_expansion", counts, steps, warmup)
+        _, _, be = ctx.shoot(w.rays, "fp64_expansion", w.pix, beta=False)
+        _, _, b64 = ctx.shoot(w.rays, "fp64", w.pix, beta=False)
+        frac = float((be != b64).sum()) / be.numel()
+        del be, b64
+    out["large"] = {"ms_per_map": 1e3 * wall / steps, "kernel_ms": sum(kms) / len(kms),
+                    "rays_per_s": w.rays.n_rays / (wall / steps),
+                    "equivalent_interactions_per_s": w.interactions / (wall / steps),
+                    "speedup_vs_fp64": fp64_seconds / (wall / steps),
+                    "misbinned_fraction_vs_fp64": frac}
+    p = W.precision_study()
+    sub = W.precision_subtile(p, 2048)
+    with raysh.Context(p.lens) as ctx:
+        ctx.shoot(sub.block(0, 0, 256, 256), "fp64_expansion", p.pix, beta=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, be = ctx.shoot(sub, "fp64_expansion", p.pix, beta=False)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, _, b64 = ctx.shoot(sub, "fp64", p.pix, beta=False)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        frac = float((be != b64).sum()) / be.numel()
+    out["precision_study_subtile"] = {"workload": "2048^2 rays x 262144 stars", "seconds": te,
+                                      "fp64_seconds": t64, "speedup_vs_fp64": t64 / te,
+                                      "misbinned_fraction_vs_fp64": frac}
+    return out
+
+
 def cpu_baseline(w, side):
     """The oracle, as it stands, on the central side x side rays."""
     from oracle import shooter as ora
@@ -264,6 +303,10 @@ def main():
     if not args.no_split:
         print("# many stars, few rays (split star sum)", file=sys.stderr, flush=True)
         out["split_star_sum"] = split_section(torch, raysh, W)
+    if not args.no_expansion:
+        print("# far-field expansion", file=sys.stderr, flush=True)
+        out["fp64_expansion"] = expansion_section(torch, raysh, W, w, wall / args.steps, args.steps,
+                                                  args.warmup)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)

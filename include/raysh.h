@@ -58,10 +58,23 @@ enum {
 
 /* Arithmetic of the star sum. */
 enum {
-    RAYSH_FP64 = 0,      /* every step in FP64 */
-    RAYSH_FP32_BULK = 1  /* star terms in FP32 on tile-relative coordinates,
-                            flushed into FP64 sums; theta, the macro term and
-                            the beta -> pixel step stay FP64 */
+    RAYSH_FP64 = 0,          /* every step in FP64 */
+    RAYSH_FP32_BULK = 1,     /* star terms in FP32 on tile-relative coordinates,
+                                flushed into FP64 sums; theta, the macro term and
+                                the beta -> pixel step stay FP64 */
+    RAYSH_FP64_EXPANSION = 2 /* FP64; for each 64 x 64 ray tile, the stars farther
+                                than rho / theta_open from the tile centre (rho:
+                                the tile's radius) enter through one local Taylor
+                                expansion of their summed term (order
+                                raysh_expansion_order()), the others directly;
+                                truncation error below theta_open^(order+1) *
+                                (1 + theta_open) / (1 - theta_open) of each far
+                                star's m_k / |theta - theta_k| (1.5e-15 at the
+                                default theta_open = 0.25, 1.6e-13 at the
+                                largest allowed, 0.3).  The
+                                paper names tree codes as the way to avoid the
+                                brute-force sum (Sec. 1); this is their
+                                single-level, per-tile form. */
 };
 
 /* The lens of Eq. (1): smooth convergence, external shear and the stars.
@@ -114,8 +127,10 @@ int raysh_set_stream(raysh_ctx *ctx, void *hip_stream);
 int64_t raysh_n_stars(const raysh_ctx *ctx);
 
 /*
- * Launch shape of the context's kernels for one precision (the autotuner's
- * knob; results do not depend on it for RAYSH_FP64).  Each lane of a
+ * Launch shape of the context's kernels for RAYSH_FP64 or RAYSH_FP32_BULK
+ * (the autotuner's knob; results do not depend on it beyond rounding for
+ * RAYSH_FP64).  RAYSH_FP64_EXPANSION has one fixed shape; these calls, the
+ * tuner and raysh_map_batch return EINVAL for it.  Each lane of a
  * 256-lane workgroup owns cx x cy rays of a (16 cx) x (16 cy) ray tile;
  * `share` stars share one reciprocal in the FP64 star sum; `star_tile`
  * stars are staged in LDS per pass in the FP32-bulk sum (the FP32 partial
@@ -124,6 +139,15 @@ int64_t raysh_n_stars(const raysh_ctx *ctx);
  * raysh_set_tile.  EINVAL if the shape is not compiled into the library.
  */
 int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int star_tile);
+
+/* Far-star criterion of RAYSH_FP64_EXPANSION for this context: a star is
+ * expanded when farther than rho / theta_open from the tile centre.  EINVAL
+ * outside (0, 0.3], the range in which the truncation error stays below
+ * 1e-12 of the error scale S. */
+int raysh_set_expansion(raysh_ctx *ctx, double theta_open);
+
+/* Number of Taylor terms minus one (the order) of RAYSH_FP64_EXPANSION. */
+int raysh_expansion_order(void);
 
 /*
  * raysh_set_star_split: split each ray's FP64 star sum over `parts`

@@ -65,8 +65,10 @@ int launch(raysh_ctx *c, const ShootParams &p, int precision, const char *what) 
         } else {
             e = raysh::launch_shoot_fp64(p, c->shape[0], c->stream);
         }
-    } else {
+    } else if (precision == RAYSH_FP32_BULK) {
         e = raysh::launch_shoot_fp32(p, c->shape[1], c->stream);
+    } else {
+        e = raysh::launch_shoot_expansion(p, c->theta_open, c->stream);
     }
     if (e != hipSuccess) return hip_error(e, what);
     return RAYSH_OK;
@@ -125,8 +127,16 @@ int validate_pixels(const raysh_pixels *p) {
 }
 
 int validate_precision(int precision) {
-    if (precision != RAYSH_FP64 && precision != RAYSH_FP32_BULK)
+    if (precision != RAYSH_FP64 && precision != RAYSH_FP32_BULK && precision != RAYSH_FP64_EXPANSION)
         return set_error(RAYSH_EINVAL, "unknown precision %d", precision);
+    return RAYSH_OK;
+}
+
+int validate_tiled_precision(int precision) {
+    if (precision != RAYSH_FP64 && precision != RAYSH_FP32_BULK)
+        return set_error(RAYSH_EINVAL,
+                         "precision %d: launch shapes, batches and tuning apply to RAYSH_FP64 and RAYSH_FP32_BULK",
+                         precision);
     return RAYSH_OK;
 }
 
@@ -246,6 +256,16 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
     return set_ok();
 }
 
+int raysh_set_expansion(raysh_ctx *ctx, double theta_open) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    if (!(theta_open > 0.0 && theta_open <= 0.3))
+        return set_error(RAYSH_EINVAL, "theta_open must lie in (0, 0.3]");
+    ctx->theta_open = theta_open;
+    return set_ok();
+}
+
+int raysh_expansion_order(void) { return raysh::expansion_order(); }
+
 int raysh_set_star_split(raysh_ctx *ctx, int parts) {
     if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
     if (parts < 0 || parts > 65536) return set_error(RAYSH_EINVAL, "star split %d outside [0, 65536]", parts);
@@ -263,7 +283,7 @@ int64_t raysh_n_stars(const raysh_ctx *ctx) { return ctx ? ctx->n_stars : 0; }
 
 int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int star_tile) {
     if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
-    if (int r = validate_precision(precision)) return r;
+    if (int r = validate_tiled_precision(precision)) return r;
     if ((precision == RAYSH_FP64 && star_tile != 0) || (precision == RAYSH_FP32_BULK && share != 0))
         return set_error(RAYSH_EINVAL, "a tile field that does not apply to precision %d is not 0",
                          precision);
@@ -278,7 +298,7 @@ int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int
 }
 
 int raysh_list_tiles(int precision, int32_t *shapes, int cap) {
-    if (validate_precision(precision) != RAYSH_OK || cap < 0 || (cap > 0 && !shapes)) {
+    if (validate_tiled_precision(precision) != RAYSH_OK || cap < 0 || (cap > 0 && !shapes)) {
         set_error(RAYSH_EINVAL, "raysh_list_tiles: bad precision, cap or NULL shapes");
         return -RAYSH_EINVAL;
     }
@@ -296,7 +316,7 @@ int raysh_list_tiles(int precision, int32_t *shapes, int cap) {
 
 int raysh_get_tile(const raysh_ctx *ctx, int precision, int *cx, int *cy, int *share, int *star_tile) {
     if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
-    if (int r = validate_precision(precision)) return r;
+    if (int r = validate_tiled_precision(precision)) return r;
     const TileShape &t = ctx->shape[precision];
     if (cx) *cx = t.cx;
     if (cy) *cy = t.cy;

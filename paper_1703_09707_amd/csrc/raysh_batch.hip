@@ -169,7 +169,7 @@ extern "C" int raysh_map_batch(raysh_ctx *const *sets, int n_sets, const raysh_r
                                const raysh_pixels *pix, int precision, int32_t *const *counts) {
     if (!sets || !rays || !pix || !counts) return set_error(RAYSH_EINVAL, "raysh_map_batch: NULL array");
     if (n_sets < 1) return set_error(RAYSH_EINVAL, "raysh_map_batch: n_sets < 1");
-    if (int r = validate_precision(precision)) return r;
+    if (int r = validate_tiled_precision(precision)) return r;
     for (int s = 0; s < n_sets; ++s) {
         if (!sets[s]) return set_error(RAYSH_EINVAL, "raysh_map_batch: set %d has no context", s);
         if (sets[s]->device != sets[0]->device)

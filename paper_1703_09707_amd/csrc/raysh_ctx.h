@@ -16,6 +16,7 @@ struct raysh_ctx {
     // default launch shapes: the fastest on MI355X for the 16384-star workload
     raysh::TileShape shape[2] = {{4, 4, 8, 0}, {4, 4, 0, 128}};
     int star_parts = 1;                    // FP64 split of each ray's star sum (0 = automatic)
+    double theta_open = 0.25;              // far-star criterion of RAYSH_FP64_EXPANSION
     double2 *d_partial = nullptr;          // split-K workspace
     size_t partial_bytes = 0;
     int n_cu = 0;
@@ -30,6 +31,7 @@ int set_ok();
 int validate_rays(const raysh_rays *r);
 int validate_pixels(const raysh_pixels *p);
 int validate_precision(int precision);
+int validate_tiled_precision(int precision);   // RAYSH_FP64 or RAYSH_FP32_BULK only
 int validate_device_ptr(const void *ptr, size_t bytes, int device, const char *name);
 
 // Lens, rays and window of one call packed for the kernels (outputs unset).

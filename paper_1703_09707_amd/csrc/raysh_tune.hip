@@ -63,7 +63,7 @@ extern "C" int raysh_autotune(raysh_ctx *ctx, const raysh_rays *rays, const rays
                               int *star_tile) {
     if (int r = validate_rays(rays)) return r;
     if (int r = validate_pixels(pix)) return r;
-    if (int r = validate_precision(precision)) return r;
+    if (int r = validate_tiled_precision(precision)) return r;
     if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
     DeviceGuard g(ctx->device);
     if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", ctx->device);

@@ -4,13 +4,15 @@
 // In complex notation (z = theta_x + i theta_y) the star term of Eq. (3) is
 // alpha_x - i alpha_y = f(z) = sum_k m_k / (z - z_k).  Around the centre c of
 // a ray tile, for a star with |c - z_k| > |z - c|,
-//   m_k / (z - z_k) = sum_{q>=0} m_k (-u_k)^q u_k (z - c)^q,  u_k = 1/(c - z_k),
-// so the far stars of a tile add up to one polynomial F(w) = sum_q B_q w^q in
-// w = z - c.  A star is far when |c - z_k| > rho / theta_open, with rho the
+//   m_k / (z - z_k) = sum_{q>=0} m_k u_k (-u_k rho)^q s^q,  u_k = 1/(c - z_k),
+// with s = (z - c) / rho, so the far stars of a tile add up to one
+// polynomial F(s) = sum_q B_q s^q (the scaling by the tile radius rho keeps
+// every |B_q| below sum m_k |u_k| theta_open^q, whatever the lattice
+// spacing).  A star is far when |c - z_k| > rho / theta_open, with rho the
 // tile's radius (centre to corner ray): then every ray of the tile has
-// |w / (c - z_k)| <= theta_open and truncating after kOrder terms leaves a
-// relative error below theta_open^(kOrder+1) / (1 - theta_open) per star
-// (about 1e-15 for theta_open = 0.25).  The near stars are summed directly,
+// |(z - c) / (c - z_k)| <= theta_open and truncating after kOrder terms leaves
+// an error below theta_open^(kOrder+1) (1 + theta_open) / (1 - theta_open)
+// times m_k / |z - z_k| per star (1.5e-15 for theta_open = 0.25).  The near stars are summed directly,
 // in index order, as in the one-pass kernel.  The paper cites hierarchical
 // tree codes as the way to avoid the brute-force sum (Sec. 1); this is the
 // single-level, per-tile form of that idea, whose truncation error stays at
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(kThreads) void expansion_fp64_kernel(ShootParams p,
     const double y_last = image_angle(p.y0, p.j0 + tile_j + kLanesY * CY - 1, p.dy);
     const double cx = 0.5 * (x_first + x_last), cy = 0.5 * (y_first + y_last);
     const double hx = 0.5 * (x_last - x_first), hy = 0.5 * (y_last - y_first);
-    const double rho = __builtin_sqrt(hx * hx + hy * hy) * (1.0 + 1e-12) + 1e-300;
+    const double rho = __builtin_sqrt(hx * hx + hy * hy) * (1.0 + 1e-12) + 1e-290;
     const double r_near = rho / theta_open;
     const double r_near2 = r_near * r_near;
 
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void expansion_fp64_kernel(ShootParams p,
             if (!near) {
                 const double inv = 1.0 / d2;
                 const double2 u = make_double2(dx * inv, -dy * inv);   // 1 / (c - z_k)
-                const double2 mu = make_double2(-u.x, -u.y);
+                const double2 mu = make_double2(-u.x * rho, -u.y * rho);   // -u rho
                 double2 t = make_double2(sm * u.x, sm * u.y);           // m u
 #pragma unroll
                 for (int q = 0; q <= kOrder; ++q) {
@@ -140,12 +142,13 @@ __global__ __launch_bounds__(kThreads) void expansion_fp64_kernel(ShootParams p,
         for (int a = 0; a < CX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
 
     if (!overflow) {   // uniform
-        // far field: Horner in w = z - c; f = alpha_x - i alpha_y
+        // far field: Horner in s = (z - c) / rho; f = alpha_x - i alpha_y
+        const double inv_rho = 1.0 / rho;
 #pragma unroll
         for (int b = 0; b < CY; ++b) {
 #pragma unroll
             for (int a = 0; a < CX; ++a) {
-                const double2 w = make_double2(tx[a] - cx, ty[b] - cy);
+                const double2 w = make_double2((tx[a] - cx) * inv_rho, (ty[b] - cy) * inv_rho);
                 double2 F = ex.B[kOrder];
                 for (int q = kOrder - 1; q >= 0; --q) {
                     const double2 bq = ex.B[q];

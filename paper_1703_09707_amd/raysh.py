@@ -18,12 +18,15 @@ LIB_PATH = os.path.join(_PKG, "libraysh.so")
 
 FP64 = 0
 FP32_BULK = 1
-PRECISIONS = {"fp64": FP64, "fp32_bulk": FP32_BULK, FP64: FP64, FP32_BULK: FP32_BULK}
+FP64_EXPANSION = 2
+PRECISIONS = {"fp64": FP64, "fp32_bulk": FP32_BULK, "fp64_expansion": FP64_EXPANSION,
+              FP64: FP64, FP32_BULK: FP32_BULK, FP64_EXPANSION: FP64_EXPANSION}
 
 OK, EINVAL, EOVERFLOW, ENOMEM, EDEVICE = 0, 1, 2, 3, 4
 _CODES = {EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"}
 
 EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", "raysh_set_star_split",
+           "raysh_set_expansion", "raysh_expansion_order",
            "raysh_list_tiles",
            "raysh_get_tile", "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch",
            "raysh_histogram_workspace", "raysh_log_mag_histogram", "raysh_mlp_create",
@@ -82,6 +85,10 @@ def load():
     lib.raysh_n_stars.restype = ctypes.c_int64
     lib.raysh_set_tile.argtypes = [P, I, I, I, I, I]
     lib.raysh_get_tile.argtypes = [P, I] + [ctypes.POINTER(I)] * 4
+    lib.raysh_set_expansion.argtypes = [P, ctypes.c_double]
+    lib.raysh_set_expansion.restype = I
+    lib.raysh_expansion_order.argtypes = []
+    lib.raysh_expansion_order.restype = I
     lib.raysh_set_star_split.argtypes = [P, I]
     lib.raysh_set_star_split.restype = I
     lib.raysh_list_tiles.argtypes = [I, ctypes.POINTER(ctypes.c_int32), I]
@@ -195,6 +202,10 @@ class Context:
 
     def set_tile(self, precision, cx, cy, share=0, star_tile=0):
         check(load().raysh_set_tile(self.handle, PRECISIONS[precision], cx, cy, share, star_tile))
+
+    def set_expansion(self, theta_open):
+        """raysh_set_expansion: far-star criterion of the expansion mode."""
+        check(load().raysh_set_expansion(self.handle, float(theta_open)))
 
     def set_star_split(self, parts):
         """raysh_set_star_split: 1 = one pass, 0 = automatic, n = n parts."""

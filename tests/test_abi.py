@@ -152,6 +152,9 @@ def test_other_argument_errors(lib):
     assert "ctx" in _err(lib)
     assert lib.raysh_sync(None) == R.EINVAL
     assert lib.raysh_set_star_split(None, 2) == R.EINVAL
+    assert lib.raysh_set_expansion(None, 0.25) == R.EINVAL
+    assert lib.raysh_expansion_order() >= 16
+    assert lib.raysh_list_tiles(2, None, 0) == -R.EINVAL
     assert lib.raysh_free(None) == R.OK
     assert lib.raysh_n_stars(None) == 0
 

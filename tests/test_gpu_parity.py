@@ -480,3 +480,87 @@ def test_large_star_field_split(torch):
         assert np.count_nonzero(_np(gb[jt, it]) != ob) == 0
         assert np.all(np.abs(_np(gx[jt, it]) - ox) <= BETA_TOL * s)
         assert np.all(np.abs(_np(gy[jt, it]) - oy) <= BETA_TOL * s)
+
+
+# ----------------------------------------------------------------- far-field expansion
+def test_expansion_matches_oracle_small(torch, small, small_oracle):
+    """RAYSH_FP64_EXPANSION holds the FP64 bar ray by ray on the 100-star
+    workload (a few far stars per tile), for several far criteria."""
+    bx, by, b, counts, n, s = small_oracle
+    with R.Context(small.lens) as ctx:
+        for theta in (0.3, 0.25, 0.1):
+            ctx.set_expansion(theta)
+            gx, gy, gb = ctx.shoot(small.rays, "fp64_expansion", small.pix)
+            assert np.all(np.abs(_np(gx) - bx) <= BETA_TOL * s), theta
+            assert np.all(np.abs(_np(gy) - by) <= BETA_TOL * s), theta
+            assert np.count_nonzero(_np(gb) != b) <= MISBIN_FP64 * b.size
+        with pytest.raises(R.RayshError):
+            ctx.set_expansion(0.0)
+        with pytest.raises(R.RayshError):
+            ctx.set_expansion(0.5)
+        with pytest.raises(R.RayshError):
+            ctx.set_tile("fp64_expansion", 4, 4)
+        with pytest.raises(R.RayshError):
+            R.map_batch([ctx], [small.rays], [small.pix], "fp64_expansion")
+
+
+def test_expansion_large_config(torch):
+    """16384 stars, 8192^2 rays: sampled rays match the oracle within the
+    FP64 bar, and the map differs from the one-pass FP64 map in at most 1e-6
+    of the rays."""
+    w = W.plain_fp64_large()
+    rng = np.random.default_rng(21)
+    ii, jj = _sample(rng, w.rays.nx, w.rays.ny, 600)
+    ox, oy, ob = ora.shoot_list(w.lens.as_tuple(), w.rays.as_tuple(), w.pix.as_tuple(), ii, jj)
+    tx, ty = ora.image_angles(w.rays.as_tuple())
+    s = np.array([ora.error_scale(w.lens.as_tuple(), tx[i], ty[j])[0] for i, j in zip(ii, jj)])
+    with R.Context(w.lens) as ctx:
+        gx, gy, gb = ctx.shoot(w.rays, "fp64_expansion", w.pix)
+        jt, it = torch.as_tensor(jj, device="cuda"), torch.as_tensor(ii, device="cuda")
+        assert np.all(np.abs(_np(gx[jt, it]) - ox) <= BETA_TOL * s)
+        assert np.all(np.abs(_np(gy[jt, it]) - oy) <= BETA_TOL * s)
+        assert np.count_nonzero(_np(gb[jt, it]) != ob) == 0
+        del gx, gy
+        _, _, b64 = ctx.shoot(w.rays, "fp64", w.pix, beta=False)
+        frac = float((gb != b64).sum()) / gb.numel()
+        _say("expansion vs one-pass FP64 misbinned fraction (large config)", frac)
+        assert frac <= MISBIN_FP64
+        m = ctx.map(w.rays, w.pix, "fp64_expansion")
+        hist = torch.bincount(gb[gb >= 0].long(), minlength=w.pix.NX * w.pix.NY)
+        assert torch.equal(hist.to(torch.int32).view(w.pix.NY, w.pix.NX), m)
+
+
+def test_expansion_precision_study_full_lattice(torch):
+    """262144 stars, the whole 16384^2 lattice: the expansion's bins differ
+    from one-pass FP64 in at most 1e-6 of the rays."""
+    w = W.precision_study()
+    with R.Context(w.lens) as ctx:
+        _, _, be = ctx.shoot(w.rays, "fp64_expansion", w.pix, beta=False)
+        _, _, b64 = ctx.shoot(w.rays, "fp64", w.pix, beta=False)
+        frac = float((be != b64).sum()) / be.numel()
+        _say("expansion vs one-pass FP64 misbinned fraction (precision study)", frac)
+        assert frac <= MISBIN_FP64
+
+
+def test_expansion_dense_cluster_falls_back(torch):
+    """More near stars than the per-tile lists hold (3000 stars within 0.3 of
+    the lattice centre): those tiles sum every star directly; the result
+    still matches the oracle ray by ray."""
+    rng = np.random.default_rng(22)
+    r = 0.3 * np.sqrt(rng.random(3000))
+    phi = 2 * np.pi * rng.random(3000)
+    far_r = 20 + 10 * rng.random(500)
+    far_p = 2 * np.pi * rng.random(500)
+    xs = np.concatenate([r * np.cos(phi), far_r * np.cos(far_p)])
+    ys = np.concatenate([r * np.sin(phi), far_r * np.sin(far_p)])
+    ms = rng.uniform(0.001, 0.002, 3500)
+    lens = (0.1, 0.1, 0.0, xs, ys, ms)
+    rays = (-1.0, -1.0, 2 / 192, 2 / 192, 192, 192, 0, 0)
+    pix = (-1.0, -1.0, 2 / 64, 2 / 64, 64, 64)
+    ox, oy, ob = ora.shoot(lens, rays, pix)
+    s = ora.error_scale_block(lens, rays)
+    with R.Context(lens) as ctx:
+        gx, gy, gb = ctx.shoot(rays, "fp64_expansion", pix)
+        assert np.all(np.abs(_np(gx) - ox) <= BETA_TOL * s)
+        assert np.all(np.abs(_np(gy) - oy) <= BETA_TOL * s)
+        assert np.count_nonzero(_np(gb) != ob) <= 1
