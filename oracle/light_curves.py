@@ -22,19 +22,23 @@ Source map (the map seen by a source of finite size):
     (i + rx, j + ry) of the map.
 
 Light curves (tracks across the source map):
-  * A track is a straight segment from a = (xa, ya) to b = (xb, yb) in
-    source-plane angles, sampled at n points s_k = k / (n - 1)
-    (s_0 = 0 when n == 1): x = xa + (xb - xa) * s_k, likewise y.
   * The source map is a grid of pixels (x0, y0, px, py, nx, ny); its
-    values sit at the pixel centres.  u = (x - x0) / px - 0.5 and
-    v = (y - y0) / py - 0.5 are the continuous centre indices.  A point
-    with 0 <= u <= nx - 1 and 0 <= v <= ny - 1 takes the bilinear
+    values sit at the pixel centres, so an angle x has the continuous
+    centre index (x - x0) / px - 0.5.
+  * A track is a straight segment from a = (xa, ya) to b = (xb, yb) in
+    source-plane angles, sampled at n points spaced evenly from a to b,
+    computed in centre-index space with each reciprocal rounded once:
+        ipx = 1 / px, inv = 1 / (n - 1) (inv = 0 when n == 1)
+        u_a = (xa - x0) * ipx - 0.5,  du = ((xb - xa) * ipx) * inv
+        u_k = u_a + du * k             (likewise v_k with y, py)
+  * A sample with 0 <= u <= nx - 1 and 0 <= v <= ny - 1 takes the bilinear
     interpolation of its four surrounding centres, i = min(floor(u), nx - 2),
     fx = u - i (likewise j, fy):
         r0 = m[j][i] + fx (m[j][i+1] - m[j][i])
         r1 = m[j+1][i] + fx (m[j+1][i+1] - m[j+1][i])
         value = r0 + fy (r1 - r0)
-    and any other point (a NaN coordinate included) is NaN.  The grid needs
+    and any other sample (a NaN coordinate included) is NaN.  A single
+    point x is evaluated at u = (x - x0) * ipx - 0.5.  The grid needs
     nx, ny >= 2.
 """
 import math
@@ -100,41 +104,59 @@ def source_map(counts, norm, profile, size, px, py):
 
 
 # ----------------------------------------------------------------- light curves
-def sample_points(xa, ya, xb, yb, n):
-    """Sample positions (n_tracks, n) of straight tracks."""
+def sample_indices(grid, xa, ya, xb, yb, n):
+    """Continuous centre indices (u, v), each (n_tracks, n), of the samples
+    of straight tracks."""
+    x0, y0, px, py = grid[:4]
+    ipx = 1.0 / px
+    ipy = 1.0 / py
+    inv = 1.0 / float(n - 1) if n > 1 else 0.0
     xa, ya, xb, yb = (np.asarray(v, np.float64)[:, None] for v in (xa, ya, xb, yb))
     k = np.arange(n, dtype=np.float64)[None, :]
-    s = k / float(n - 1) if n > 1 else np.zeros_like(k)
-    return xa + (xb - xa) * s, ya + (yb - ya) * s
+    ua = (xa - x0) * ipx - 0.5
+    va = (ya - y0) * ipy - 0.5
+    du = ((xb - xa) * ipx) * inv
+    dv = ((yb - ya) * ipy) * inv
+    return ua + du * k, va + dv * k
 
 
-def interpolate(mu_s, grid, x, y):
-    """Bilinear value of the source map at the points (x, y); NaN outside."""
-    x0, y0, px, py, nx, ny = grid
+def interpolate_indices(mu_s, u, v):
+    """Bilinear value of the source map at continuous centre indices
+    (u, v); NaN outside the hull of the centres."""
     mu_s = np.asarray(mu_s, np.float64)
-    assert mu_s.shape == (ny, nx) and nx >= 2 and ny >= 2
-    x = np.asarray(x, np.float64)
-    y = np.asarray(y, np.float64)
-    out = np.full(x.shape, np.nan)
-    for idx in np.ndindex(x.shape):
-        u = (x[idx] - x0) / px - 0.5
-        v = (y[idx] - y0) / py - 0.5
-        if not (0.0 <= u <= nx - 1 and 0.0 <= v <= ny - 1):
+    ny, nx = mu_s.shape
+    assert nx >= 2 and ny >= 2
+    u = np.asarray(u, np.float64)
+    v = np.asarray(v, np.float64)
+    out = np.full(u.shape, np.nan)
+    for idx in np.ndindex(u.shape):
+        uu, vv = float(u[idx]), float(v[idx])
+        if not (0.0 <= uu <= nx - 1 and 0.0 <= vv <= ny - 1):
             continue
-        i = min(int(math.floor(u)), nx - 2)
-        j = min(int(math.floor(v)), ny - 2)
-        fx = u - i
-        fy = v - j
+        i = min(int(math.floor(uu)), nx - 2)
+        j = min(int(math.floor(vv)), ny - 2)
+        fx = uu - i
+        fy = vv - j
         r0 = mu_s[j, i] + fx * (mu_s[j, i + 1] - mu_s[j, i])
         r1 = mu_s[j + 1, i] + fx * (mu_s[j + 1, i + 1] - mu_s[j + 1, i])
         out[idx] = r0 + fy * (r1 - r0)
     return out
 
 
+def interpolate(mu_s, grid, x, y):
+    """Bilinear value of the source map at the angles (x, y); NaN outside."""
+    x0, y0, px, py, nx, ny = grid
+    assert np.shape(mu_s) == (ny, nx)
+    u = (np.asarray(x, np.float64) - x0) * (1.0 / px) - 0.5
+    v = (np.asarray(y, np.float64) - y0) * (1.0 / py) - 0.5
+    return interpolate_indices(mu_s, u, v)
+
+
 def light_curves(mu_s, grid, xa, ya, xb, yb, n_samples):
     """Light curves (n_tracks, n_samples) of straight tracks across mu_s."""
-    x, y = sample_points(xa, ya, xb, yb, n_samples)
-    return interpolate(mu_s, grid, x, y)
+    assert np.shape(mu_s) == (grid[5], grid[4])
+    u, v = sample_indices(grid, xa, ya, xb, yb, n_samples)
+    return interpolate_indices(mu_s, u, v)
 
 
 def source_grid(pix, profile, size):

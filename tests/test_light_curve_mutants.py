@@ -14,14 +14,18 @@ import test_light_curve_oracle_pins as pins
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "light_curves.py")
 
 MUTANTS = {
-    "centre offset dropped": ("u = (x[idx] - x0) / px - 0.5", "u = (x[idx] - x0) / px"),
+    "centre offset dropped": ("ua = (xa - x0) * ipx - 0.5", "ua = (xa - x0) * ipx"),
+    "centre offset dropped (points)": ("u = (np.asarray(x, np.float64) - x0) * (1.0 / px) - 0.5",
+                                       "u = (np.asarray(x, np.float64) - x0) * (1.0 / px)"),
+    "x pixel size for y": ("ipy = 1.0 / py", "ipy = 1.0 / px"),
+    "step from the wrong end": ("\n    du = ((xb - xa) * ipx) * inv", "\n    du = ((xb - x0) * ipx) * inv"),
     "fx used for fy": ("out[idx] = r0 + fy * (r1 - r0)", "out[idx] = r0 + fx * (r1 - r0)"),
     "row neighbour for column neighbour": ("r0 = mu_s[j, i] + fx * (mu_s[j, i + 1] - mu_s[j, i])",
                                            "r0 = mu_s[j, i] + fx * (mu_s[j + 1, i] - mu_s[j, i])"),
-    "no clamp at the far edge": ("i = min(int(math.floor(u)), nx - 2)", "i = int(math.floor(u))"),
-    "open hull": ("if not (0.0 <= u <= nx - 1 and", "if not (0.0 < u < nx - 1 and"),
-    "hull on the map edge": ("0.0 <= v <= ny - 1)", "-0.5 <= v <= ny - 0.5)"),
-    "sample spacing": ("s = k / float(n - 1) if n > 1", "s = k / float(n) if n > 1"),
+    "no clamp at the far edge": ("i = min(int(math.floor(uu)), nx - 2)", "i = int(math.floor(uu))"),
+    "open hull": ("if not (0.0 <= uu <= nx - 1 and", "if not (0.0 < uu < nx - 1 and"),
+    "hull on the map edge": ("0.0 <= vv <= ny - 1)", "-0.5 <= vv <= ny - 0.5)"),
+    "sample spacing": ("inv = 1.0 / float(n - 1) if n > 1", "inv = 1.0 / float(n) if n > 1"),
     "strict disk": ("return a * a + b * b <= radius * radius", "return a * a + b * b < radius * radius"),
     "disk row uses px": ("b = float(l) * py", "b = float(l) * px"),
     "disk normalised by its box": ("/ float(len(offs))", "/ float((2 * rx + 1) * (2 * ry + 1))"),

@@ -80,13 +80,27 @@ def pin_hull_and_nan(L):
 
 
 def pin_sample_positions(L):
-    x, y = L.sample_points(np.array([0.5, -1.0]), np.array([0.25, 2.0]), np.array([-1.5, 3.0]),
-                           np.array([1.25, 2.0]), 5)
-    np.testing.assert_array_equal(x, [[0.5, 0.0, -0.5, -1.0, -1.5], [-1.0, 0.0, 1.0, 2.0, 3.0]])
-    np.testing.assert_array_equal(y, [[0.25, 0.5, 0.75, 1.0, 1.25], [2.0, 2.0, 2.0, 2.0, 2.0]])
-    x, y = L.sample_points(np.array([0.5]), np.array([0.25]), np.array([9.0]), np.array([9.0]), 1)
-    np.testing.assert_array_equal(x, [[0.5]])
-    np.testing.assert_array_equal(y, [[0.25]])
+    """Samples sit at the centre indices of points spaced evenly from a to
+    b (exact for dyadic tracks), and a single sample at a."""
+    grid = _grid()
+    x0, y0, px, py = grid[:4]
+    xa, ya, xb, yb = [0.5, -1.0], [0.25, 2.0], [-1.5, 1.0], [1.25, 2.0]
+    u, v = L.sample_indices(grid, np.array(xa), np.array(ya), np.array(xb), np.array(yb), 5)
+    for t in range(2):
+        for k in range(5):
+            x = Fraction(xa[t]) + (Fraction(xb[t]) - Fraction(xa[t])) * Fraction(k, 4)
+            y = Fraction(ya[t]) + (Fraction(yb[t]) - Fraction(ya[t])) * Fraction(k, 4)
+            assert u[t, k] == float((x - Fraction(x0)) / Fraction(px) - Fraction(1, 2))
+            assert v[t, k] == float((y - Fraction(y0)) / Fraction(py) - Fraction(1, 2))
+    u, v = L.sample_indices(grid, np.array([0.5]), np.array([0.25]), np.array([9.0]), np.array([9.0]), 1)
+    assert u.shape == (1, 1)
+    assert u[0, 0] == float((Fraction(0.5) - Fraction(x0)) / Fraction(px) - Fraction(1, 2))
+    assert v[0, 0] == float((Fraction(0.25) - Fraction(y0)) / Fraction(py) - Fraction(1, 2))
+    # tracks of many samples end within rounding of b
+    u, v = L.sample_indices(grid, np.array([-1.2]), np.array([0.8]), np.array([1.3]), np.array([1.7]), 1001)
+    assert abs(u[0, -1] - ((1.3 - x0) / px - 0.5)) < 1e-12
+    assert abs(v[0, -1] - ((1.7 - y0) / py - 0.5)) < 1e-12
+    assert abs(u[0, 500] - ((0.05 - x0) / px - 0.5)) < 1e-12
 
 
 def pin_disk_offsets(L):
