@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 FLOP_PER_INTERACTION = 10
 PROFILE = os.path.join(ROOT, "profiles", "shoot_fp64_kernel_plain-fp64-large.txt")
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0              # MI355X HBM3E
 
 
 def parse():
@@ -46,6 +47,7 @@ def parse():
     ap.add_argument("--no-precision", action="store_true", help="skip the precision study")
     ap.add_argument("--no-split", action="store_true", help="skip the many-stars/few-rays study")
     ap.add_argument("--no-expansion", action="store_true", help="skip the far-field expansion study")
+    ap.add_argument("--no-light-curves", action="store_true", help="skip the light-curve timing")
     ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
     ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
     ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
@@ -201,6 +203,48 @@ def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup):
     return out
 
 
+def light_curve_section(torch, raysh, W, steps):
+    """Light curves: the map of the large configuration seen by a Gaussian
+    source of 2 pixels, then 2^20 straight tracks of 256 samples across it.
+    The light-curve kernel is a gather bound by HBM: its algorithmic bytes
+    are the curves written, the track end points read and the source map
+    read once."""
+    lw = W.light_curves_large()
+    w = lw.maps
+    norm = (w.rays.dx * w.rays.dy) / (w.pix.Px * w.pix.Py)
+    with raysh.Context(w.lens) as ctx:
+        counts = ctx.map(w.rays, w.pix, "fp64")
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731
+    mu, grid = raysh.source_map(counts, w.pix, norm, lw.profile, lw.size)
+    tracks = [torch.from_numpy(a).cuda() for a in W.light_curve_tracks(grid, lw.n_tracks, lw.length)]
+    curves = torch.empty((lw.n_tracks, lw.n_samples), dtype=torch.float64, device="cuda")
+    raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves)
+    torch.cuda.synchronize()
+    sm, lc = [], []
+    for _ in range(steps):
+        a, b, c = ev(), ev(), ev()
+        a.record(stream)
+        mu, grid = raysh.source_map(counts, w.pix, norm, lw.profile, lw.size)
+        b.record(stream)
+        raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves)
+        c.record(stream)
+        torch.cuda.synchronize()
+        sm.append(a.elapsed_time(b))
+        lc.append(b.elapsed_time(c))
+    lc_ms = sum(lc) / len(lc)
+    samples = lw.n_tracks * lw.n_samples
+    nbytes = samples * 8 + lw.n_tracks * 32 + mu.numel() * 8
+    achieved = nbytes / (lc_ms * 1e-3) / 1e9
+    return {"workload": lw.name, "samples": samples,
+            "source_map_ms": sum(sm) / len(sm),
+            "light_curve_kernel_ms": lc_ms,
+            "samples_per_s": samples / (lc_ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "kernel": "light_curve_kernel",
+                         "bytes_per_launch": nbytes}}
+
+
 def cpu_baseline(w, side):
     """The oracle, as it stands, on the central side x side rays."""
     from oracle import shooter as ora
@@ -307,6 +351,9 @@ def main():
         print("# far-field expansion", file=sys.stderr, flush=True)
         out["fp64_expansion"] = expansion_section(torch, raysh, W, w, wall / args.steps, args.steps,
                                                   args.warmup)
+    if not args.no_light_curves:
+        print("# light curves", file=sys.stderr, flush=True)
+        out["light_curves"] = light_curve_section(torch, raysh, W, args.steps)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)

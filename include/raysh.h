@@ -66,7 +66,9 @@ enum {
                                 than rho / theta_open from the tile centre (rho:
                                 the tile's radius) enter through one local Taylor
                                 expansion of their summed term (order
-                                raysh_expansion_order()), the others directly;
+                                raysh_expansion_order()), built once per block of
+                                tiles and re-centred on each tile (see
+                                raysh_set_expansion_block), the others directly;
                                 truncation error below theta_open^(order+1) *
                                 (1 + theta_open) / (1 - theta_open) of each far
                                 star's m_k / |theta - theta_k| (1.5e-15 at the
@@ -145,6 +147,16 @@ int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int
  * outside (0, 0.3], the range in which the truncation error stays below
  * 1e-12 of the error scale S. */
 int raysh_set_expansion(raysh_ctx *ctx, double theta_open);
+
+/* Workgroup shape of RAYSH_FP64_EXPANSION for this context: each workgroup
+ * expands the stars far from a block of block x block tiles of 64 x 64 rays
+ * once, then re-tests only that block's near stars for each tile (block 1:
+ * one tile, one test).  0 (the default) picks the block by a cost model:
+ * a workgroup costs about n_stars + 16384 block^2 star-equivalents, and
+ * workgroups run in rounds of two per compute unit.  The block
+ * changes the order of floating-point operations, not the accuracy bound.
+ * EINVAL for a NULL context or a block other than 0, 1, 2 or 4. */
+int raysh_set_expansion_block(raysh_ctx *ctx, int block);
 
 /* Number of Taylor terms minus one (the order) of RAYSH_FP64_EXPANSION. */
 int raysh_expansion_order(void);
@@ -268,6 +280,83 @@ int raysh_log_mag_histogram(const int32_t *counts, int32_t nx, int32_t ny, doubl
                             double px, double py, double mu_ref, int32_t nbins, double lo, double hi,
                             void *workspace, size_t workspace_bytes, uint32_t *bin_counts, float *hist,
                             void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Simulated light curves.  A magnification map and a model of the source's
+ * size and brightness profile give simulated light curves, which the
+ * Bayesian Monte Carlo analysis compares with observed ones (Sec. 1).  The
+ * paper fixes neither the profile nor the tracks; the library offers the two
+ * profiles below and straight tracks.
+ * ---------------------------------------------------------------------- */
+enum {
+    RAYSH_SOURCE_GAUSSIAN = 0,  /* circular Gaussian of width `size`: taps at
+                                   pixel offsets |k| <= r = ceil(3 size / p),
+                                   normalised per axis, applied rows then
+                                   columns (as raysh_log_mag_histogram) */
+    RAYSH_SOURCE_DISK = 1       /* uniform disk of radius `size`: the pixels at
+                                   offsets (k, l) with (k px)^2 + (l py)^2 <=
+                                   size^2 in FP64; the value is (norm * S) / n,
+                                   S the integer sum of their counts, n their
+                                   number; rx, ry are the largest |k| on row 0
+                                   and |l| on column 0 in the disk */
+};
+
+/* Half-widths (rx, ry) of a profile on a map of nx x ny pixels of size
+ * px x py; the source map has (nx - 2 rx) x (ny - 2 ry) pixels.  rx, ry may
+ * be NULL.  EINVAL on an unknown profile, a size, pixel or map size that is
+ * not finite and > 0, a source whose reach (3 size for the Gaussian, size
+ * for the disk) is not below nx px and ny py, or a source map smaller than
+ * 2 x 2 pixels. */
+int raysh_source_map_shape(int32_t nx, int32_t ny, int profile, double size, double px, double py,
+                           int32_t *rx, int32_t *ry);
+
+/* Device workspace, in bytes, that raysh_source_map needs (0 for a
+ * non-positive size). */
+size_t raysh_source_map_workspace(int32_t nx, int32_t ny);
+
+/*
+ * raysh_source_map: the magnification map seen by a source of the given
+ * profile.  counts: device int32 map [ny][nx] (as written by raysh_map);
+ * norm = (dx*dy)/(px*py), so that counts * norm is the magnification.
+ * mu_s: device FP64 [ny - 2 ry][nx - 2 rx]; its pixel (i, j) is pixel
+ * (i + rx, j + ry) of the map, so its own grid starts at
+ * (x0 + rx px, y0 + ry py) of the map's window.  All arithmetic is FP64.
+ * workspace: device memory of raysh_source_map_workspace(nx, ny) bytes.
+ * Asynchronous on hip_stream (NULL = null stream), on the counts' device.
+ * Errors as raysh_source_map_shape, plus EINVAL on NULL or non-device
+ * buffers, a short workspace or a norm that is not finite and > 0, and
+ * EOVERFLOW above 2^31-1 pixels.
+ */
+int raysh_source_map(const int32_t *counts, int32_t nx, int32_t ny, double norm, int profile, double size,
+                     double px, double py, void *workspace, size_t workspace_bytes, double *mu_s,
+                     void *hip_stream);
+
+/*
+ * raysh_light_curves: n_tracks straight tracks across a source map.
+ *   mu_s:  device FP64 [grid->ny][grid->nx]; its values sit at the pixel
+ *          centres (grid->x0 + (i + 0.5) grid->px, grid->y0 + (j + 0.5) grid->py);
+ *          grid->nx, grid->ny >= 2;
+ *   track t runs from (xa[t], ya[t]) to (xb[t], yb[t]) (device FP64 arrays
+ *          of n_tracks, source-plane angles) and is sampled at n_samples
+ *          evenly spaced points, in the map's centre-index space: with
+ *          ipx = 1 / grid->px and inv = 1 / (n_samples - 1) (0 when
+ *          n_samples == 1), each rounded once,
+ *            u_k = ((xa - x0) ipx - 0.5) + (((xb - xa) ipx) inv) k,
+ *          likewise v_k with y, y0 and py;
+ *   curves: device FP64 [n_tracks][n_samples]: a sample with
+ *          0 <= u <= nx - 1 and 0 <= v <= ny - 1 takes the bilinear
+ *          interpolation of its four surrounding centres (i = min(floor(u),
+ *          nx - 2), fx = u - i, r0 = m[j][i] + fx (m[j][i+1] - m[j][i]),
+ *          r1 likewise on row j+1, value r0 + fy (r1 - r0)); any other
+ *          sample is NaN.  Every product and sum is rounded on its own.
+ * Asynchronous on hip_stream, on mu_s's device.  n_tracks == 0 is a no-op.
+ * EINVAL on a bad grid, n_tracks < 0, n_samples outside [1, 2^24], NULL or
+ * non-device buffers; EOVERFLOW above 2^31-1 map pixels or (2^31-1) * 256
+ * samples.
+ */
+int raysh_light_curves(const double *mu_s, const raysh_pixels *grid, int64_t n_tracks, int32_t n_samples,
+                       const double *xa, const double *ya, const double *xb, const double *yb, double *curves,
+                       void *hip_stream);
 
 /*
  * The network: layers n_in -> n_hidden -> n_hidden -> n_out, GELU (erf

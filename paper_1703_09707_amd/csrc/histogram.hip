@@ -14,59 +14,22 @@
 #include <limits>
 
 #include "raysh_ctx.h"
+#include "smooth.h"
 
 namespace {
 
-constexpr int kHistThreads = 256;
 constexpr int kMaxBins = 4096;
-
-// taps[0..2r] of one axis: exp(-0.5 ((k - r) P / sigma)^2), then divided by
-// their sum (one workgroup).
-__global__ __launch_bounds__(kHistThreads) void taps_kernel(double sigma, double pixel, int r,
-                                                            double *taps) {
-    __shared__ double part[kHistThreads];
-    const int n = 2 * r + 1;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += kHistThreads) {
-        const double d = ((double)(k - r) * pixel) / sigma;
-        const double g = exp(-0.5 * (d * d));
-        taps[k] = g;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {   // sum in index order, as a plain loop does
-        for (int k = 0; k < n; ++k) s += taps[k];
-        part[0] = s;
-    }
-    __syncthreads();
-    const double total = part[0];
-    for (int k = threadIdx.x; k < n; k += kHistThreads) taps[k] = taps[k] / total;
-}
-
-// tmp[j][i] = sum_k gx[k] * (counts[j][i + k] * norm), i < wx, taps in order.
-__global__ __launch_bounds__(kHistThreads) void smooth_rows_kernel(const int32_t *__restrict__ counts,
-                                                                   int nx, int ny, double norm,
-                                                                   const double *__restrict__ gx,
-                                                                   int rx, int wx, double *__restrict__ tmp) {
-#pragma clang fp contract(off)
-    const int64_t idx = (int64_t)blockIdx.x * kHistThreads + threadIdx.x;
-    if (idx >= (int64_t)wx * ny) return;
-    const int j = (int)(idx / wx), i = (int)(idx % wx);
-    const int32_t *row = counts + (int64_t)j * nx + i;
-    double acc = 0.0;
-    for (int k = 0; k <= 2 * rx; ++k) acc = acc + gx[k] * ((double)row[k] * norm);
-    tmp[idx] = acc;
-}
 
 // Column pass for pixel (i, j) of the valid interior, then its bin, counted
 // in an LDS histogram and added to the global bin counts.
-__global__ __launch_bounds__(kHistThreads) void smooth_cols_hist_kernel(
+__global__ __launch_bounds__(kSmoothThreads) void smooth_cols_hist_kernel(
     const double *__restrict__ tmp, int wx, int wy, const double *__restrict__ gy, int ry, double mu_ref,
     int nbins, double lo, double hi, unsigned *__restrict__ bins) {
 #pragma clang fp contract(off)
     __shared__ unsigned h[kMaxBins];
-    for (int b = threadIdx.x; b < nbins; b += kHistThreads) h[b] = 0;
+    for (int b = threadIdx.x; b < nbins; b += kSmoothThreads) h[b] = 0;
     __syncthreads();
-    const int64_t idx = (int64_t)blockIdx.x * kHistThreads + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * kSmoothThreads + threadIdx.x;
     if (idx < (int64_t)wx * wy) {
         const int j = (int)(idx / wx), i = (int)(idx % wx);
         const double *col = tmp + (int64_t)j * wx + i;
@@ -82,7 +45,7 @@ __global__ __launch_bounds__(kHistThreads) void smooth_cols_hist_kernel(
         atomicAdd(&h[b], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += kHistThreads)
+    for (int b = threadIdx.x; b < nbins; b += kSmoothThreads)
         if (h[b]) atomicAdd(&bins[b], h[b]);
 }
 
@@ -103,7 +66,6 @@ __global__ void normalise_kernel(const unsigned *bins, int n, float *hist) {
         hist[b] = total ? (float)((double)bins[b] / (double)total) : 0.0f;
 }
 
-int taps_radius(double sigma, double pixel) { return (int)std::ceil(3.0 * sigma / pixel); }
 
 }  // namespace
 
@@ -156,14 +118,14 @@ extern "C" int raysh_log_mag_histogram(const int32_t *counts, int32_t nx, int32_
     double *tmp = (double *)workspace;                      // ny * wx
     double *gxt = tmp + (size_t)ny * wx;                    // 2 rx + 1
     double *gyt = gxt + (2 * rx + 1);                       // 2 ry + 1
-    hipLaunchKernelGGL(taps_kernel, dim3(1), dim3(kHistThreads), 0, s, sigma, px, rx, gxt);
-    hipLaunchKernelGGL(taps_kernel, dim3(1), dim3(kHistThreads), 0, s, sigma, py, ry, gyt);
+    hipLaunchKernelGGL(taps_kernel, dim3(1), dim3(kSmoothThreads), 0, s, sigma, px, rx, gxt);
+    hipLaunchKernelGGL(taps_kernel, dim3(1), dim3(kSmoothThreads), 0, s, sigma, py, ry, gyt);
     hipLaunchKernelGGL(zero_bins_kernel, dim3((nbins + 255) / 256), dim3(256), 0, s, bin_counts, nbins);
     const int64_t n1 = (int64_t)wx * ny, n2 = (int64_t)wx * wy;
-    hipLaunchKernelGGL(smooth_rows_kernel, dim3((unsigned)((n1 + kHistThreads - 1) / kHistThreads)),
-                       dim3(kHistThreads), 0, s, counts, nx, ny, norm, gxt, rx, wx, tmp);
-    hipLaunchKernelGGL(smooth_cols_hist_kernel, dim3((unsigned)((n2 + kHistThreads - 1) / kHistThreads)),
-                       dim3(kHistThreads), 0, s, tmp, wx, wy, gyt, ry, mu_ref, nbins, lo, hi,
+    hipLaunchKernelGGL(smooth_rows_kernel, dim3((unsigned)((n1 + kSmoothThreads - 1) / kSmoothThreads)),
+                       dim3(kSmoothThreads), 0, s, counts, nx, ny, norm, gxt, rx, wx, tmp);
+    hipLaunchKernelGGL(smooth_cols_hist_kernel, dim3((unsigned)((n2 + kSmoothThreads - 1) / kSmoothThreads)),
+                       dim3(kSmoothThreads), 0, s, tmp, wx, wy, gyt, ry, mu_ref, nbins, lo, hi,
                        (unsigned *)bin_counts);
     if (hist) hipLaunchKernelGGL(normalise_kernel, dim3(1), dim3(256), 0, s, (const unsigned *)bin_counts, nbins, hist);
     hipError_t e = hipGetLastError();

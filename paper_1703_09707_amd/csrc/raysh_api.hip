@@ -68,7 +68,10 @@ int launch(raysh_ctx *c, const ShootParams &p, int precision, const char *what) 
     } else if (precision == RAYSH_FP32_BULK) {
         e = raysh::launch_shoot_fp32(p, c->shape[1], c->stream);
     } else {
-        e = raysh::launch_shoot_expansion(p, c->theta_open, c->stream);
+        e = raysh::launch_shoot_expansion(
+            p, c->theta_open,
+            c->expansion_block ? c->expansion_block : raysh::expansion_block(p.nx, p.ny, c->n_stars, c->n_cu),
+            c->stream);
     }
     if (e != hipSuccess) return hip_error(e, what);
     return RAYSH_OK;
@@ -261,6 +264,14 @@ int raysh_set_expansion(raysh_ctx *ctx, double theta_open) {
     if (!(theta_open > 0.0 && theta_open <= 0.3))
         return set_error(RAYSH_EINVAL, "theta_open must lie in (0, 0.3]");
     ctx->theta_open = theta_open;
+    return set_ok();
+}
+
+int raysh_set_expansion_block(raysh_ctx *ctx, int block) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "raysh_set_expansion_block: NULL context");
+    if (block != 0 && block != 1 && block != 2 && block != 4)
+        return set_error(RAYSH_EINVAL, "expansion block must be 0 (automatic), 1, 2 or 4");
+    ctx->expansion_block = block;
     return set_ok();
 }
 

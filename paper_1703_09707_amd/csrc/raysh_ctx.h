@@ -17,6 +17,7 @@ struct raysh_ctx {
     raysh::TileShape shape[2] = {{4, 4, 8, 0}, {4, 4, 0, 128}};
     int star_parts = 1;                    // FP64 split of each ray's star sum (0 = automatic)
     double theta_open = 0.25;              // far-star criterion of RAYSH_FP64_EXPANSION
+    int expansion_block = 0;               // tiles per side of its workgroups (0 = automatic)
     double2 *d_partial = nullptr;          // split-K workspace
     size_t partial_bytes = 0;
     int n_cu = 0;

@@ -83,9 +83,11 @@ hipError_t launch_batch_fp32(const BatchArgs &b, const TileShape &shape, int blo
 int batch_fp64_blocks_per_cu(const TileShape &shape);
 int batch_fp32_blocks_per_cu(const TileShape &shape);
 
-// FP64 with the far field of each ray tile as a local expansion
-// (shoot_expansion.hip); tiles of 64 x 64 rays.
-hipError_t launch_shoot_expansion(const ShootParams &p, double theta_open, hipStream_t s);
+// FP64 with the far field as local expansions (shoot_expansion.hip); tiles
+// of 64 x 64 rays, one workgroup per block of `block` x `block` tiles
+// (1, 2 or 4).  expansion_block picks the block for a lattice block.
+hipError_t launch_shoot_expansion(const ShootParams &p, double theta_open, int block, hipStream_t s);
+int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu);
 int expansion_order();
 
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);

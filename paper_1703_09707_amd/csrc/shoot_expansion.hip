@@ -1,26 +1,37 @@
-// FP64 ray shooting with the far field of each ray tile summed as a local
-// (Taylor) expansion; a faster route to the sum of Eq. (3) for many stars.
+// FP64 ray shooting with the far field of the star sum as local (Taylor)
+// expansions; a faster route to the sum of Eq. (3) for many stars.
 //
 // In complex notation (z = theta_x + i theta_y) the star term of Eq. (3) is
-// alpha_x - i alpha_y = f(z) = sum_k m_k / (z - z_k).  Around the centre c of
-// a ray tile, for a star with |c - z_k| > |z - c|,
+// alpha_x - i alpha_y = f(z) = sum_k m_k / (z - z_k).  Around a centre c,
+// for a star with |c - z_k| > |z - c|,
 //   m_k / (z - z_k) = sum_{q>=0} m_k u_k (-u_k rho)^q s^q,  u_k = 1/(c - z_k),
-// with s = (z - c) / rho, so the far stars of a tile add up to one
-// polynomial F(s) = sum_q B_q s^q (the scaling by the tile radius rho keeps
-// every |B_q| below sum m_k |u_k| theta_open^q, whatever the lattice
+// with s = (z - c) / rho, so the far stars of a region add up to one
+// polynomial F(s) = sum_q B_q s^q (the scaling by the region's radius rho
+// keeps every |B_q| below sum m_k |u_k| theta_open^q, whatever the lattice
 // spacing).  A star is far when |c - z_k| > rho / theta_open, with rho the
-// tile's radius (centre to corner ray): then every ray of the tile has
-// |(z - c) / (c - z_k)| <= theta_open and truncating after kOrder terms leaves
-// an error below theta_open^(kOrder+1) (1 + theta_open) / (1 - theta_open)
-// times m_k / |z - z_k| per star (1.5e-15 for theta_open = 0.25).  The near stars are summed directly,
-// in index order, as in the one-pass kernel.  The paper cites hierarchical
-// tree codes as the way to avoid the brute-force sum (Sec. 1); this is the
-// single-level, per-tile form of that idea, whose truncation error stays at
-// the level of FP64 rounding.
+// region's radius (centre to corner ray): then every ray of the region has
+// |(z - c) / (c - z_k)| <= theta_open and truncating after kOrder terms
+// leaves an error below theta_open^(kOrder+1) (1 + theta_open) /
+// (1 - theta_open) times m_k / |z - z_k| per star (1.5e-15 for
+// theta_open = 0.25).  Near stars are summed directly, in index order.  The
+// paper cites hierarchical tree codes as the way to avoid the brute-force
+// sum (Sec. 1); this is a two-level form of that idea, on the ray side,
+// whose truncation error stays at the level of FP64 rounding.
 //
-// Work per tile: every star once (near test, and kOrder complex
-// multiply-adds for a far one), then per ray a Horner evaluation of F and
-// the near stars.  Ray tiles are (16 CX) x (16 CY) as in the one-pass kernel.
+// Two levels.  A workgroup owns a block of L x L ray tiles (a tile is
+// 64 x 64 rays, 4 x 4 per lane as in the one-pass kernel).  It expands the
+// stars far from the whole block once (every star is visited once per
+// block, not once per tile), keeping the block's near stars in lists.  For
+// each tile it then
+//   * re-centres the block's polynomial on the tile (the shift of a
+//     polynomial is exact algebra: no new truncation),
+//   * re-tests only the block's near stars: those far from the tile join
+//     its polynomial, the rest are summed directly,
+//   * evaluates the polynomial for its rays (Horner), adds the near stars
+//     and bins the rays.
+// With L = 1 the block is the tile and the second test is skipped.  If a
+// block has more near stars than its lists hold, its tiles sum every star
+// directly.
 #include "ray_common.h"
 
 namespace raysh {
@@ -30,71 +41,80 @@ namespace {
 constexpr int kOrder = 24;            // Taylor terms B_0 .. B_kOrder
 constexpr int kWaves = kThreads / 64;
 constexpr int kNearPerWave = 512;     // near-star list capacity of each wave
+constexpr int kCX = 4, kCY = 4;       // rays per lane
+constexpr int kTile = kLanesX * kCX;  // 64 rays per tile side
+static_assert(kLanesX * kCX == kLanesY * kCY, "square tiles");
 
 struct ExpShared {
-    double2 B[kOrder + 1];                      // the tile's expansion coefficients
+    double2 A[kOrder + 1];                      // the block's coefficients
+    double2 B[kOrder + 1];                      // the current tile's coefficients
     double2 part[kWaves][kOrder + 1];           // per-wave partial sums
-    int near_idx[kWaves][kNearPerWave];         // near stars, each wave's in index order
-    int n_near[kWaves];
+    int outer_idx[kWaves][kNearPerWave];        // the block's near stars, each wave's in index order
+    int outer_n[kWaves];
+    int inner_idx[kWaves][kNearPerWave];        // the tile's near stars (a subset of the block's)
+    int inner_n[kWaves];
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(__builtin_fma(a.x, b.x, -a.y * b.y), __builtin_fma(a.x, b.y, a.y * b.x));
 }
 
-template <int CX, int CY>
-__global__ __launch_bounds__(kThreads) void expansion_fp64_kernel(ShootParams p, double theta_open) {
-    __shared__ BinShared sh;
-    __shared__ ExpShared ex;
-    bin_shared_init(sh);
-
-    const int lx = threadIdx.x % kLanesX;
-    const int ly = threadIdx.x / kLanesX;
-    const int64_t tiles_x = p.tiles_x;
-    const int64_t tile = blockIdx.x;
-    const int64_t tile_i = (tile % tiles_x) * (kLanesX * CX);
-    const int64_t tile_j = (tile / tiles_x) * (kLanesY * CY);
-    double tx[CX], ty[CY];
-#pragma unroll
-    for (int a = 0; a < CX; ++a) tx[a] = image_angle(p.x0, p.i0 + tile_i + lx + kLanesX * a, p.dx);
-#pragma unroll
-    for (int b = 0; b < CY; ++b) ty[b] = image_angle(p.y0, p.j0 + tile_j + ly + kLanesY * b, p.dy);
-
-    // tile centre and radius from its first and last lattice points
-    const double x_first = image_angle(p.x0, p.i0 + tile_i, p.dx);
-    const double x_last = image_angle(p.x0, p.i0 + tile_i + kLanesX * CX - 1, p.dx);
-    const double y_first = image_angle(p.y0, p.j0 + tile_j, p.dy);
-    const double y_last = image_angle(p.y0, p.j0 + tile_j + kLanesY * CY - 1, p.dy);
-    const double cx = 0.5 * (x_first + x_last), cy = 0.5 * (y_first + y_last);
+// Centre and radius (centre to corner ray, slightly enlarged) of the square
+// of w x w lattice points whose first point is (i, j) of the block.
+__device__ __forceinline__ void region(const ShootParams &p, int64_t i, int64_t j, int w, double &cx,
+                                       double &cy, double &rho) {
+    const double x_first = image_angle(p.x0, p.i0 + i, p.dx);
+    const double x_last = image_angle(p.x0, p.i0 + i + w - 1, p.dx);
+    const double y_first = image_angle(p.y0, p.j0 + j, p.dy);
+    const double y_last = image_angle(p.y0, p.j0 + j + w - 1, p.dy);
+    cx = 0.5 * (x_first + x_last);
+    cy = 0.5 * (y_first + y_last);
     const double hx = 0.5 * (x_last - x_first), hy = 0.5 * (y_last - y_first);
-    const double rho = __builtin_sqrt(hx * hx + hy * hy) * (1.0 + 1e-12) + 1e-290;
-    const double r_near = rho / theta_open;
-    const double r_near2 = r_near * r_near;
+    rho = __builtin_sqrt(hx * hx + hy * hy) * (1.0 + 1e-12) + 1e-290;
+}
 
-    // --- far stars into the expansion, near stars into per-wave lists
-    const ConstStar *st = const_stars(uniform_ptr(p.stars));
-    const int n = uniform(p.n_stars);
+// One pass over `count` stars split into four contiguous quarters, one per
+// wave.  Entry e is star e (LIST false) or the e-th entry of the
+// concatenated per-wave lists in_idx / in_n (LIST true).  A star farther
+// than sqrt(r_near2) from (cx, cy) adds m u (-u rho)^q to the lane's
+// coefficients; a nearer one is appended to its wave's out list, so that
+// the concatenated out lists stay in star index order.  out_n counts every
+// near star, also beyond the capacity.
+template <bool LIST>
+__device__ __forceinline__ void p2l_pass(const ConstStar *st, int count, const int (*in_idx)[kNearPerWave],
+                                         const int *in_n, double cx, double cy, double rho, double r_near2,
+                                         double2 (&acc)[kOrder + 1], int (*out_idx)[kNearPerWave], int *out_n) {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int per_wave = (n + kWaves - 1) / kWaves;
-    const int w0 = wave * per_wave < n ? wave * per_wave : n;
-    const int w1 = w0 + per_wave < n ? w0 + per_wave : n;
-    double2 acc[kOrder + 1];
-#pragma unroll
-    for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
-    int count = 0;   // this wave's near stars so far (uniform in the wave)
+    const int per_wave = (count + kWaves - 1) / kWaves;
+    const int w0 = wave * per_wave < count ? wave * per_wave : count;
+    const int w1 = w0 + per_wave < count ? w0 + per_wave : count;
+    int n0 = 0, n1 = 0, n2 = 0;
+    if (LIST) {
+        n0 = in_n[0];
+        n1 = n0 + in_n[1];
+        n2 = n1 + in_n[2];
+    }
+    int found = 0;   // this wave's near stars so far (uniform in the wave)
     for (int base = w0; base < w1; base += 64) {
-        const int k = base + lane;
+        const int e = base + lane;
         bool near = false;
-        if (k < w1) {
+        int k = 0;
+        if (e < w1) {
+            if (LIST) {
+                k = e < n0 ? in_idx[0][e] : e < n1 ? in_idx[1][e - n0] : e < n2 ? in_idx[2][e - n1]
+                                                                                : in_idx[3][e - n2];
+            } else {
+                k = e;
+            }
             const double sx = st[k].x, sy = st[k].y, sm = st[k].m;
             const double dx = cx - sx, dy = cy - sy;
             const double d2 = dx * dx + dy * dy;
             near = d2 <= r_near2;
             if (!near) {
                 const double inv = 1.0 / d2;
-                const double2 u = make_double2(dx * inv, -dy * inv);   // 1 / (c - z_k)
-                const double2 mu = make_double2(-u.x * rho, -u.y * rho);   // -u rho
-                double2 t = make_double2(sm * u.x, sm * u.y);           // m u
+                const double2 u = make_double2(dx * inv, -dy * inv);        // 1 / (c - z_k)
+                const double2 mu = make_double2(-u.x * rho, -u.y * rho);    // -u rho
+                double2 t = make_double2(sm * u.x, sm * u.y);               // m u
 #pragma unroll
                 for (int q = 0; q <= kOrder; ++q) {
                     acc[q].x += t.x;
@@ -105,13 +125,19 @@ __global__ __launch_bounds__(kThreads) void expansion_fp64_kernel(ShootParams p,
         }
         const unsigned long long ball = __ballot(near);
         if (near) {
-            const int pos = count + __popcll(ball & ((1ull << lane) - 1ull));
-            if (pos < kNearPerWave) ex.near_idx[wave][pos] = k;
+            const int pos = found + __popcll(ball & ((1ull << lane) - 1ull));
+            if (pos < kNearPerWave) out_idx[wave][pos] = k;
         }
-        count += __popcll(ball);
+        found += __popcll(ball);
     }
-    if (lane == 0) ex.n_near[wave] = count;
-    // per-wave reduction of the coefficients (fixed order), then across waves
+    if (lane == 0) out_n[wave] = found;
+}
+
+// Workgroup sum of the lanes' coefficients into dst (added to it when ADD),
+// in a fixed order: a cross-lane tree in each wave, then the waves in turn.
+template <bool ADD>
+__device__ __forceinline__ void reduce_coeffs(double2 (&acc)[kOrder + 1], ExpShared &ex, double2 *dst) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
     for (int q = 0; q <= kOrder; ++q) {
         double vx = acc[q].x, vy = acc[q].y;
@@ -129,96 +155,212 @@ __global__ __launch_bounds__(kThreads) void expansion_fp64_kernel(ShootParams p,
             s.x += ex.part[w][threadIdx.x].x;
             s.y += ex.part[w][threadIdx.x].y;
         }
-        ex.B[threadIdx.x] = s;
+        if (ADD) {
+            s.x += dst[threadIdx.x].x;
+            s.y += dst[threadIdx.x].y;
+        }
+        dst[threadIdx.x] = s;
     }
     __syncthreads();
-    bool overflow = false;
-    for (int w = 0; w < kWaves; ++w) overflow |= ex.n_near[w] > kNearPerWave;
+}
 
-    double ax[CY][CX], ay[CY][CX];
-#pragma unroll
-    for (int b = 0; b < CY; ++b)
-#pragma unroll
-        for (int a = 0; a < CX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
+// Coefficient r of the block's polynomial re-centred on a tile: with
+// s = a + b s' (a = (c - C) / R, b = rho / R),
+//   B_r = b^r sum_{q=r}^{kOrder} A_q C(q, r) a^(q - r),
+// summed by Horner in a from q = kOrder down.  The binomials are exact
+// integers (at most C(24, 12)), built by exact integer steps.
+__device__ __forceinline__ double2 shift_coeff(const double2 *A, int r, double2 a, double b) {
+    double c = 1.0;   // C(kOrder, r)
+    for (int i = 1; i <= r; ++i) c = (c * (double)(kOrder - r + i)) / (double)i;
+    double2 acc = make_double2(A[kOrder].x * c, A[kOrder].y * c);
+    for (int q = kOrder - 1; q >= r; --q) {
+        c = (c * (double)(q + 1 - r)) / (double)(q + 1);   // C(q, r) from C(q + 1, r)
+        const double2 t = cmul(acc, a);
+        acc = make_double2(t.x + A[q].x * c, t.y + A[q].y * c);
+    }
+    double br = 1.0;
+    for (int i = 0; i < r; ++i) br *= b;
+    return make_double2(acc.x * br, acc.y * br);
+}
 
-    if (!overflow) {   // uniform
-        // far field: Horner in s = (z - c) / rho; f = alpha_x - i alpha_y
-        const double inv_rho = 1.0 / rho;
+// The FP64 term of star k for a lane's rays (reciprocal plus one Newton
+// step, as in the one-pass kernel).
+__device__ __forceinline__ void direct_star(const ConstStar *st, int k, const double (&tx)[kCX],
+                                            const double (&ty)[kCY], double (&ax)[kCY][kCX],
+                                            double (&ay)[kCY][kCX]) {
+    const double sx = st[k].x, sy = st[k].y, sm = st[k].m;
 #pragma unroll
-        for (int b = 0; b < CY; ++b) {
+    for (int b = 0; b < kCY; ++b) {
+        const double ey = ty[b] - sy;
 #pragma unroll
-            for (int a = 0; a < CX; ++a) {
-                const double2 w = make_double2((tx[a] - cx) * inv_rho, (ty[b] - cy) * inv_rho);
-                double2 F = ex.B[kOrder];
-                for (int q = kOrder - 1; q >= 0; --q) {
-                    const double2 bq = ex.B[q];
-                    F = make_double2(__builtin_fma(F.x, w.x, __builtin_fma(-F.y, w.y, bq.x)),
-                                     __builtin_fma(F.x, w.y, __builtin_fma(F.y, w.x, bq.y)));
-                }
-                ax[b][a] += F.x;
-                ay[b][a] -= F.y;
-            }
-        }
-        // near stars, directly, in index order
-        for (int w = 0; w < kWaves; ++w) {
-            const int cnt = uniform(ex.n_near[w]);
-            for (int i = 0; i < cnt; ++i) {
-                const int k = uniform(ex.near_idx[w][i]);
-                const double sx = st[k].x, sy = st[k].y, sm = st[k].m;
-#pragma unroll
-                for (int b = 0; b < CY; ++b) {
-                    const double ey = ty[b] - sy;
-#pragma unroll
-                    for (int a = 0; a < CX; ++a) {
-                        const double ex_ = tx[a] - sx;
-                        const double r2 = __builtin_fma(ex_, ex_, ey * ey);
-                        double y = __builtin_amdgcn_rcp(r2);
-                        const double e = __builtin_fma(-r2, y, 1.0);
-                        y = __builtin_fma(y, e, y);
-                        const double wgt = sm * y;
-                        ax[b][a] = __builtin_fma(wgt, ex_, ax[b][a]);
-                        ay[b][a] = __builtin_fma(wgt, ey, ay[b][a]);
-                    }
-                }
-            }
-        }
-    } else {
-        // too many near stars for the lists: this tile sums every star directly
-        for (int k = 0; k < n; ++k) {
-            const double sx = st[k].x, sy = st[k].y, sm = st[k].m;
-#pragma unroll
-            for (int b = 0; b < CY; ++b) {
-                const double ey = ty[b] - sy;
-#pragma unroll
-                for (int a = 0; a < CX; ++a) {
-                    const double ex_ = tx[a] - sx;
-                    const double r2 = __builtin_fma(ex_, ex_, ey * ey);
-                    double y = __builtin_amdgcn_rcp(r2);
-                    const double e = __builtin_fma(-r2, y, 1.0);
-                    y = __builtin_fma(y, e, y);
-                    const double wgt = sm * y;
-                    ax[b][a] = __builtin_fma(wgt, ex_, ax[b][a]);
-                    ay[b][a] = __builtin_fma(wgt, ey, ay[b][a]);
-                }
-            }
+        for (int a = 0; a < kCX; ++a) {
+            const double ex_ = tx[a] - sx;
+            const double r2 = __builtin_fma(ex_, ex_, ey * ey);
+            double y = __builtin_amdgcn_rcp(r2);
+            const double e = __builtin_fma(-r2, y, 1.0);
+            y = __builtin_fma(y, e, y);
+            const double wgt = sm * y;
+            ax[b][a] = __builtin_fma(wgt, ex_, ax[b][a]);
+            ay[b][a] = __builtin_fma(wgt, ey, ay[b][a]);
         }
     }
-    finish_tile<CX, CY>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
+}
+
+// Two workgroups per compute unit: the compiler keeps to 256 VGPRs.
+template <int L>
+__global__ __launch_bounds__(kThreads, 2) void expansion_fp64_kernel(ShootParams p, double theta_open,
+                                                                  int blocks_x) {
+    __shared__ BinShared sh;
+    __shared__ ExpShared ex;
+    bin_shared_init(sh);
+
+    const int lx = threadIdx.x % kLanesX;
+    const int ly = threadIdx.x / kLanesX;
+    const int64_t b_i = (int64_t)(blockIdx.x % blocks_x) * (kTile * L);
+    const int64_t b_j = (int64_t)(blockIdx.x / blocks_x) * (kTile * L);
+    const ConstStar *st = const_stars(uniform_ptr(p.stars));
+    const int n = uniform(p.n_stars);
+    const double inv_theta = 1.0 / theta_open;
+
+    // --- the block: far stars into A, near stars into the outer lists
+    double bcx, bcy, brho;
+    region(p, b_i, b_j, kTile * L, bcx, bcy, brho);
+    {
+        double2 acc[kOrder + 1];
+#pragma unroll
+        for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
+        const double r_near = brho * inv_theta;
+        p2l_pass<false>(st, n, nullptr, nullptr, bcx, bcy, brho, r_near * r_near, acc, ex.outer_idx, ex.outer_n);
+        reduce_coeffs<false>(acc, ex, ex.A);   // its barriers also publish outer_n
+    }
+    bool overflow = false;
+    int n_outer = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        overflow |= ex.outer_n[w] > kNearPerWave;
+        n_outer += ex.outer_n[w];
+    }
+
+    for (int t = 0; t < L * L; ++t) {   // uniform trip count
+        const int64_t tile_i = b_i + (int64_t)(t % L) * kTile;
+        const int64_t tile_j = b_j + (int64_t)(t / L) * kTile;
+        if (tile_i >= p.nx || tile_j >= p.ny) continue;   // uniform: no ray of this tile is in the lattice block
+
+        const int(*near_idx)[kNearPerWave] = ex.outer_idx;
+        const int *near_n = ex.outer_n;
+        double cx = bcx, cy = bcy, rho = brho;
+        if (!overflow) {   // uniform
+            if constexpr (L == 1) {
+                if (threadIdx.x <= kOrder) ex.B[threadIdx.x] = ex.A[threadIdx.x];
+            } else {
+                region(p, tile_i, tile_j, kTile, cx, cy, rho);
+                const double inv_brho = 1.0 / brho;
+                if (threadIdx.x <= kOrder)
+                    ex.B[threadIdx.x] = shift_coeff(ex.A, threadIdx.x,
+                                                    make_double2((cx - bcx) * inv_brho, (cy - bcy) * inv_brho),
+                                                    rho * inv_brho);
+                double2 acc[kOrder + 1];
+#pragma unroll
+                for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
+                const double r_near = rho * inv_theta;
+                p2l_pass<true>(st, n_outer, ex.outer_idx, ex.outer_n, cx, cy, rho, r_near * r_near, acc,
+                               ex.inner_idx, ex.inner_n);
+                __syncthreads();                        // B is written before it is added to
+                reduce_coeffs<true>(acc, ex, ex.B);     // its barriers also publish inner_n
+                near_idx = ex.inner_idx;
+                near_n = ex.inner_n;
+            }
+            __syncthreads();
+        }
+
+        double tx[kCX], ty[kCY];
+#pragma unroll
+        for (int a = 0; a < kCX; ++a) tx[a] = image_angle(p.x0, p.i0 + tile_i + lx + kLanesX * a, p.dx);
+#pragma unroll
+        for (int b = 0; b < kCY; ++b) ty[b] = image_angle(p.y0, p.j0 + tile_j + ly + kLanesY * b, p.dy);
+        double ax[kCY][kCX], ay[kCY][kCX];
+#pragma unroll
+        for (int b = 0; b < kCY; ++b)
+#pragma unroll
+            for (int a = 0; a < kCX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
+
+        if (!overflow) {
+            // far field: Horner in s = (z - c) / rho; f = alpha_x - i alpha_y
+            const double inv_rho = 1.0 / rho;
+#pragma unroll
+            for (int b = 0; b < kCY; ++b) {
+#pragma unroll
+                for (int a = 0; a < kCX; ++a) {
+                    const double2 w = make_double2((tx[a] - cx) * inv_rho, (ty[b] - cy) * inv_rho);
+                    double2 F = ex.B[kOrder];
+                    for (int q = kOrder - 1; q >= 0; --q) {
+                        const double2 bq = ex.B[q];
+                        F = make_double2(__builtin_fma(F.x, w.x, __builtin_fma(-F.y, w.y, bq.x)),
+                                         __builtin_fma(F.x, w.y, __builtin_fma(F.y, w.x, bq.y)));
+                    }
+                    ax[b][a] += F.x;
+                    ay[b][a] -= F.y;
+                }
+            }
+            // near stars, directly, in index order
+            for (int w = 0; w < kWaves; ++w) {
+                const int cnt = uniform(near_n[w]);
+                for (int i = 0; i < cnt; ++i) direct_star(st, uniform(near_idx[w][i]), tx, ty, ax, ay);
+            }
+        } else {
+            // too many near stars for the lists: every star directly
+            for (int k = 0; k < n; ++k) direct_star(st, k, tx, ty, ax, ay);
+        }
+        finish_tile<kCX, kCY>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
+        __syncthreads();   // the bin window, red[], B and the inner lists are reused by the next tile
+        bin_shared_init(sh);
+    }
+}
+
+template <int L>
+hipError_t launch_level(const ShootParams &p, double theta_open, int64_t tiles_x, int64_t tiles_y,
+                        hipStream_t s) {
+    const int64_t bx = (tiles_x + L - 1) / L, by = (tiles_y + L - 1) / L;
+    hipLaunchKernelGGL((expansion_fp64_kernel<L>), dim3((unsigned)(bx * by)), dim3(kThreads), 0, s, p, theta_open,
+                       (int)bx);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 int expansion_order() { return kOrder; }
 
-hipError_t launch_shoot_expansion(const ShootParams &p, double theta_open, hipStream_t s) {
-    constexpr int CX = 4, CY = 4;
+// The block that minimises a simple cost model: a workgroup costs about
+// N* + 16384 L^2 star-equivalents (its pass over all stars, then L^2 tiles
+// of Horner steps, near stars and binning, measured on MI355X), and the
+// workgroups run in rounds of two per compute unit.
+int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu) {
+    const int64_t tx = (nx + kTile - 1) / kTile, ty = (ny + kTile - 1) / kTile;
+    const int64_t slots = 2 * (int64_t)(n_cu > 0 ? n_cu : 256);
+    int best = 1;
+    double best_cost = 0.0;
+    for (int L : {1, 2, 4}) {
+        const int64_t blocks = ((tx + L - 1) / L) * ((ty + L - 1) / L);
+        const int64_t rounds = (blocks + slots - 1) / slots;
+        const double cost = (double)rounds * ((double)n_stars + 16384.0 * L * L);
+        if (L == 1 || cost < best_cost) {
+            best = L;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+hipError_t launch_shoot_expansion(const ShootParams &p, double theta_open, int block, hipStream_t s) {
     ShootParams q = p;
-    q.tiles_x = (int32_t)((p.nx + kLanesX * CX - 1) / (kLanesX * CX));
-    const int64_t tiles_y = (p.ny + kLanesY * CY - 1) / (kLanesY * CY);
-    const int64_t blocks = (int64_t)q.tiles_x * tiles_y;
-    hipLaunchKernelGGL((expansion_fp64_kernel<CX, CY>), dim3((unsigned)blocks), dim3(kThreads), 0, s, q,
-                       theta_open);
-    return hipGetLastError();
+    const int64_t tiles_x = (p.nx + kTile - 1) / kTile;
+    const int64_t tiles_y = (p.ny + kTile - 1) / kTile;
+    q.tiles_x = (int32_t)tiles_x;
+    switch (block) {
+        case 1: return launch_level<1>(q, theta_open, tiles_x, tiles_y, s);
+        case 2: return launch_level<2>(q, theta_open, tiles_x, tiles_y, s);
+        case 4: return launch_level<4>(q, theta_open, tiles_x, tiles_y, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace raysh

@@ -22,14 +22,21 @@ FP64_EXPANSION = 2
 PRECISIONS = {"fp64": FP64, "fp32_bulk": FP32_BULK, "fp64_expansion": FP64_EXPANSION,
               FP64: FP64, FP32_BULK: FP32_BULK, FP64_EXPANSION: FP64_EXPANSION}
 
+SOURCE_GAUSSIAN = 0
+SOURCE_DISK = 1
+PROFILES = {"gaussian": SOURCE_GAUSSIAN, "disk": SOURCE_DISK,
+            SOURCE_GAUSSIAN: SOURCE_GAUSSIAN, SOURCE_DISK: SOURCE_DISK}
+
 OK, EINVAL, EOVERFLOW, ENOMEM, EDEVICE = 0, 1, 2, 3, 4
 _CODES = {EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"}
 
 EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", "raysh_set_star_split",
-           "raysh_set_expansion", "raysh_expansion_order",
+           "raysh_set_expansion", "raysh_set_expansion_block", "raysh_expansion_order",
            "raysh_list_tiles",
            "raysh_get_tile", "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch",
-           "raysh_histogram_workspace", "raysh_log_mag_histogram", "raysh_mlp_create",
+           "raysh_histogram_workspace", "raysh_log_mag_histogram",
+           "raysh_source_map_shape", "raysh_source_map_workspace", "raysh_source_map", "raysh_light_curves",
+           "raysh_mlp_create",
            "raysh_mlp_n_params", "raysh_mlp_get_params", "raysh_mlp_forward", "raysh_mlp_gradient",
            "raysh_mlp_adam_step", "raysh_mlp_train_step", "raysh_mlp_sync", "raysh_mlp_free",
            "raysh_sync", "raysh_free", "raysh_last_error")
@@ -87,6 +94,8 @@ def load():
     lib.raysh_get_tile.argtypes = [P, I] + [ctypes.POINTER(I)] * 4
     lib.raysh_set_expansion.argtypes = [P, ctypes.c_double]
     lib.raysh_set_expansion.restype = I
+    lib.raysh_set_expansion_block.argtypes = [P, I]
+    lib.raysh_set_expansion_block.restype = I
     lib.raysh_expansion_order.argtypes = []
     lib.raysh_expansion_order.restype = I
     lib.raysh_set_star_split.argtypes = [P, I]
@@ -99,6 +108,16 @@ def load():
     lib.raysh_log_mag_histogram.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, D, D, D, D,
                                             ctypes.c_int32, D, D, P, ctypes.c_size_t, P, P, P]
     lib.raysh_log_mag_histogram.restype = I
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.raysh_source_map_shape.argtypes = [ctypes.c_int32, ctypes.c_int32, I, D, D, D, i32p, i32p]
+    lib.raysh_source_map_shape.restype = I
+    lib.raysh_source_map_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.raysh_source_map_workspace.restype = ctypes.c_size_t
+    lib.raysh_source_map.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, I, D, D, D, P, ctypes.c_size_t, P, P]
+    lib.raysh_source_map.restype = I
+    lib.raysh_light_curves.argtypes = [P, ctypes.POINTER(Pixels), ctypes.c_int64, ctypes.c_int32,
+                                       P, P, P, P, P, P]
+    lib.raysh_light_curves.restype = I
     F = ctypes.c_float
     lib.raysh_mlp_create.argtypes = [ctypes.POINTER(P), I, P, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32, P]
@@ -207,6 +226,11 @@ class Context:
         """raysh_set_expansion: far-star criterion of the expansion mode."""
         check(load().raysh_set_expansion(self.handle, float(theta_open)))
 
+    def set_expansion_block(self, block):
+        """raysh_set_expansion_block: tiles per side of the expansion mode's
+        workgroups (0 = automatic, 1, 2 or 4)."""
+        check(load().raysh_set_expansion_block(self.handle, int(block)))
+
     def set_star_split(self, parts):
         """raysh_set_star_split: 1 = one pass, 0 = automatic, n = n parts."""
         check(load().raysh_set_star_split(self.handle, int(parts)))
@@ -309,3 +333,48 @@ def map_batch(contexts, rays, pix, precision="fp64", counts=None):
     C = (ctypes.c_void_p * n)(*[c.data_ptr() for c in counts])
     check(load().raysh_map_batch(H, n, R, P, PRECISIONS[precision], C))
     return counts
+
+
+def source_map_shape(nx, ny, profile, size, px, py):
+    """raysh_source_map_shape: half-widths (rx, ry) of a source profile."""
+    rx, ry = ctypes.c_int32(), ctypes.c_int32()
+    check(load().raysh_source_map_shape(int(nx), int(ny), PROFILES[profile], float(size), float(px), float(py),
+                                        ctypes.byref(rx), ctypes.byref(ry)))
+    return rx.value, ry.value
+
+
+def source_map(counts, pix, norm, profile="gaussian", size=0.05, stream=None):
+    """raysh_source_map: the map seen by a source of the given profile.
+    counts: int32 device map (NY, NX) of the window pix.  Returns the FP64
+    source map (NY - 2 ry, NX - 2 rx) and its own pixel grid
+    (x0 + rx Px, y0 + ry Py, Px, Py, NX - 2 rx, NY - 2 ry)."""
+    torch = _torch()
+    p = pixels_struct(pix)
+    assert counts.dtype == torch.int32 and counts.is_contiguous() and tuple(counts.shape) == (p.ny, p.nx)
+    rx, ry = source_map_shape(p.nx, p.ny, profile, size, p.px, p.py)
+    lib = load()
+    dev = counts.device
+    ws = torch.empty(lib.raysh_source_map_workspace(p.nx, p.ny), dtype=torch.uint8, device=dev)
+    out = torch.empty((p.ny - 2 * ry, p.nx - 2 * rx), dtype=torch.float64, device=dev)
+    check(lib.raysh_source_map(_ptr(counts), p.nx, p.ny, float(norm), PROFILES[profile], float(size), p.px, p.py,
+                               _ptr(ws), ws.numel(), _ptr(out), _stream_handle(torch, dev, stream)))
+    grid = (p.x0 + rx * p.px, p.y0 + ry * p.py, p.px, p.py, p.nx - 2 * rx, p.ny - 2 * ry)
+    return out, grid
+
+
+def light_curves(mu_s, grid, xa, ya, xb, yb, n_samples, out=None, stream=None):
+    """raysh_light_curves: tracks (xa, ya) -> (xb, yb) (FP64 device arrays)
+    sampled at n_samples points across the source map mu_s of pixel grid
+    `grid`.  Returns FP64 (n_tracks, n_samples), NaN outside the map."""
+    torch = _torch()
+    g = pixels_struct(grid)
+    n = int(xa.numel())
+    for a in (mu_s, xa, ya, xb, yb):
+        assert a.dtype == torch.float64 and a.is_contiguous()
+    assert tuple(mu_s.shape) == (g.ny, g.nx) and all(int(a.numel()) == n for a in (ya, xb, yb))
+    if out is None:
+        out = torch.empty((n, int(n_samples)), dtype=torch.float64, device=mu_s.device)
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == n * int(n_samples)
+    check(load().raysh_light_curves(_ptr(mu_s), ctypes.byref(g), n, int(n_samples), _ptr(xa), _ptr(ya),
+                                    _ptr(xb), _ptr(yb), _ptr(out), _stream_handle(torch, mu_s.device, stream)))
+    return out

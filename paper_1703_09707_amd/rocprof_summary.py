@@ -26,6 +26,7 @@ KERNEL_SOURCES = {
     "partial_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "finish_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "expansion_fp64_kernel": ["csrc/shoot_expansion.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+    "light_curve_kernel": ["csrc/light_curves.hip", "csrc/smooth.h"],
 }
 
 
@@ -110,7 +111,7 @@ def main(argv=None):
     lines.append("kernel trace (rocprofv3 --kernel-trace --stats), durations in us:")
     k_avg = None
     for name, calls, total, avg, pct in kernel_stats(a.stats)[:8]:
-        short = name.split("(")[0][-70:]
+        short = name.replace("(anonymous namespace)::", "").split("(")[0][-70:]
         lines.append(f"  {short:70s} calls {calls:4d} avg {avg:14.1f} total {total:16.1f} {pct:6.2f}%")
         if a.kernel in name and k_avg is None:
             k_avg = avg

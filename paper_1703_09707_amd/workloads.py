@@ -287,3 +287,44 @@ def mean_magnification(kappa: float, gamma1: float, gamma2: float) -> float:
     """1 / |det A| for the mean lens matrix: the textbook mean magnification
     of a smooth sheet, also the large-field mean for a star field."""
     return 1.0 / abs((1.0 - kappa) ** 2 - gamma1 ** 2 - gamma2 ** 2)
+
+
+# ----------------------------------------------------------------- light curves
+def light_curve_tracks(grid, n_tracks: int, length: float, seed: int = BASE_SEED + 5):
+    """Straight tracks of the given length across a source map's pixel grid
+    grid = (x0, y0, px, py, nx, ny): centres uniform in the hull of the
+    pixel centres shrunk by length / 2 on every side, directions uniform.
+    Returns FP64 arrays (xa, ya, xb, yb)."""
+    x0, y0, px, py, nx, ny = grid
+    lo_x, hi_x = x0 + 0.5 * px + 0.5 * length, x0 + (nx - 0.5) * px - 0.5 * length
+    lo_y, hi_y = y0 + 0.5 * py + 0.5 * length, y0 + (ny - 0.5) * py - 0.5 * length
+    if not (lo_x < hi_x and lo_y < hi_y):
+        raise ValueError("tracks longer than the map")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cx = rng.uniform(lo_x, hi_x, n_tracks)
+    cy = rng.uniform(lo_y, hi_y, n_tracks)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n_tracks)
+    hx, hy = 0.5 * length * np.cos(phi), 0.5 * length * np.sin(phi)
+    return cx - hx, cy - hy, cx + hx, cy + hy
+
+
+@dataclasses.dataclass
+class LightCurveWorkload:
+    """Light curves across the map of a ray-shooting workload."""
+    name: str
+    maps: Workload
+    profile: str
+    size: float
+    n_tracks: int
+    n_samples: int
+    length: float
+
+
+def light_curves_large() -> LightCurveWorkload:
+    """The 1024^2 map of plain-fp64-large (20 x 20 Einstein angles), a
+    Gaussian source of width 2 pixels, and 2^20 tracks of 2 Einstein angles
+    sampled at 256 points (about 0.4 pixel apart)."""
+    w = plain_fp64_large()
+    return LightCurveWorkload("light-curves-large: 2^20 tracks x 256 samples on the 1024^2 map of "
+                              "plain-fp64-large, Gaussian source of 2 pixels", w, "gaussian",
+                              2.0 * w.pix.Px, 1 << 20, 256, 2.0)

@@ -153,6 +153,7 @@ def test_other_argument_errors(lib):
     assert lib.raysh_sync(None) == R.EINVAL
     assert lib.raysh_set_star_split(None, 2) == R.EINVAL
     assert lib.raysh_set_expansion(None, 0.25) == R.EINVAL
+    assert lib.raysh_set_expansion_block(None, 1) == R.EINVAL
     assert lib.raysh_expansion_order() >= 16
     assert lib.raysh_list_tiles(2, None, 0) == -R.EINVAL
     assert lib.raysh_free(None) == R.OK
@@ -199,3 +200,45 @@ def test_histogram_and_mlp_argument_errors(lib):
     assert lib.raysh_mlp_adam_step(None, 1e-3, 0.9, 0.999, 1e-8) == R.EINVAL
     assert lib.raysh_mlp_free(None) == R.OK
     assert lib.raysh_mlp_n_params(None) == 0
+
+
+@pytest.mark.parametrize("profile,size,px,py", [(0, 0.05, 0.03125, 0.0625), (0, 0.1, 0.0195, 0.0195),
+                                                (1, 1.375, 0.5, 0.25), (1, 3.0, 1.0, 1.0),
+                                                (1, 0.3, 0.125, 0.0625), (1, 0.01, 0.1, 0.1)])
+def test_source_map_shape_matches_oracle(lib, profile, size, px, py):
+    """The library's source half-widths (host code) equal the oracle's."""
+    from oracle import light_curves as LC
+    rx, ry = R.source_map_shape(200, 150, profile, size, px, py)
+    assert (rx, ry) == LC.source_radii(profile, size, px, py)
+
+
+def test_source_map_and_light_curve_argument_errors(lib):
+    dummy = ctypes.c_void_p(1)
+    rx, ry = ctypes.c_int32(), ctypes.c_int32()
+    s = lib.raysh_source_map_shape
+    for args, msg in [((64, 64, 2, 0.1, 0.1, 0.1), "profile"), ((0, 64, 0, 0.1, 0.1, 0.1), "map size"),
+                      ((64, 64, 0, -0.1, 0.1, 0.1), "source size"), ((64, 64, 1, math.nan, 0.1, 0.1), "source size"),
+                      ((64, 64, 0, 0.1, 0.0, 0.1), "pixel"), ((64, 64, 0, 3.0, 0.1, 0.1), "larger than the map"),
+                      ((64, 64, 1, 6.5, 0.1, 0.1), "larger than the map"), ((64, 64, 1, 3.2, 0.1, 0.1), "2 x 2")]:
+        assert s(*args, ctypes.byref(rx), ctypes.byref(ry)) == R.EINVAL, args
+        assert msg in _err(lib), (args, _err(lib))
+    assert s(64, 64, 1, 0.25, 0.1, 0.1, None, None) == R.OK
+    assert lib.raysh_source_map_workspace(0, 4) == 0
+    assert lib.raysh_source_map_workspace(10, 10) >= 8 * 100
+    sm = lib.raysh_source_map
+    assert sm(dummy, 64, 64, 0.0, 0, 0.1, 0.1, 0.1, dummy, 1 << 20, dummy, None) == R.EINVAL
+    assert "norm" in _err(lib)
+    assert sm(None, 64, 64, 1.0, 0, 0.1, 0.1, 0.1, dummy, 1 << 20, dummy, None) == R.EINVAL
+    assert sm(dummy, 64, 64, 1.0, 0, 0.1, 0.1, 0.1, dummy, 16, dummy, None) == R.EINVAL
+    assert "workspace" in _err(lib)
+    lc = lib.raysh_light_curves
+    g = R.Pixels(0.0, 0.0, 0.1, 0.1, 16, 16)
+    assert lc(dummy, None, 4, 8, dummy, dummy, dummy, dummy, dummy, None) == R.EINVAL
+    assert lc(dummy, ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 1, 16)), 4, 8, dummy, dummy, dummy, dummy, dummy,
+              None) == R.EINVAL
+    assert lc(dummy, ctypes.byref(g), -1, 8, dummy, dummy, dummy, dummy, dummy, None) == R.EINVAL
+    assert lc(dummy, ctypes.byref(g), 4, 0, dummy, dummy, dummy, dummy, dummy, None) == R.EINVAL
+    assert lc(dummy, ctypes.byref(g), 4, (1 << 24) + 1, dummy, dummy, dummy, dummy, dummy, None) == R.EINVAL
+    assert lc(dummy, ctypes.byref(g), 1 << 40, 1 << 20, dummy, dummy, dummy, dummy, dummy, None) == R.EOVERFLOW
+    assert lc(dummy, ctypes.byref(g), 4, 8, None, dummy, dummy, dummy, dummy, None) == R.EINVAL
+    assert lc(None, ctypes.byref(g), 0, 8, None, None, None, None, None, None) == R.OK   # no tracks: no-op

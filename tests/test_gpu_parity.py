@@ -483,25 +483,51 @@ def test_large_star_field_split(torch):
 
 
 # ----------------------------------------------------------------- far-field expansion
-def test_expansion_matches_oracle_small(torch, small, small_oracle):
+@pytest.mark.parametrize("block", [1, 2, 4])
+def test_expansion_matches_oracle_small(torch, small, small_oracle, block):
     """RAYSH_FP64_EXPANSION holds the FP64 bar ray by ray on the 100-star
-    workload (a few far stars per tile), for several far criteria."""
+    workload (a few far stars per tile), for several far criteria and each
+    workgroup block (1, 2 or 4 tiles per side; 1000^2 rays are 16 x 16
+    tiles, the last row and column ragged)."""
     bx, by, b, counts, n, s = small_oracle
     with R.Context(small.lens) as ctx:
+        ctx.set_expansion_block(block)
         for theta in (0.3, 0.25, 0.1):
             ctx.set_expansion(theta)
             gx, gy, gb = ctx.shoot(small.rays, "fp64_expansion", small.pix)
             assert np.all(np.abs(_np(gx) - bx) <= BETA_TOL * s), theta
             assert np.all(np.abs(_np(gy) - by) <= BETA_TOL * s), theta
             assert np.count_nonzero(_np(gb) != b) <= MISBIN_FP64 * b.size
+        m, nb = ctx.map(small.rays, small.pix, "fp64_expansion", n_binned=True)
+        assert 0.5 * (np.abs(_np(m) - counts).sum() + abs(nb - n)) <= MISBIN_FP64 * b.size
         with pytest.raises(R.RayshError):
             ctx.set_expansion(0.0)
         with pytest.raises(R.RayshError):
             ctx.set_expansion(0.5)
         with pytest.raises(R.RayshError):
+            ctx.set_expansion_block(3)
+        with pytest.raises(R.RayshError):
             ctx.set_tile("fp64_expansion", 4, 4)
         with pytest.raises(R.RayshError):
             R.map_batch([ctx], [small.rays], [small.pix], "fp64_expansion")
+
+
+@pytest.mark.parametrize("block", [2, 4])
+@pytest.mark.parametrize("i0,j0,nx,ny", [(0, 0, 300, 200), (37, 501, 130, 499), (999, 0, 1, 1000),
+                                         (5, 5, 64, 64), (0, 0, 0, 10)])
+def test_expansion_ragged_blocks(torch, small, small_oracle, block, i0, j0, nx, ny):
+    """Lattice blocks that fill a workgroup's tiles partly (or not at all)."""
+    bx, by, b, _, _, s = small_oracle
+    blk = small.rays.block(i0, j0, nx, ny)
+    with R.Context(small.lens) as ctx:
+        ctx.set_expansion_block(block)
+        gx, gy, gb = ctx.shoot(blk, "fp64_expansion", small.pix)
+        if nx * ny == 0:
+            return
+        sl = (slice(j0, j0 + ny), slice(i0, i0 + nx))
+        assert np.all(np.abs(_np(gx) - bx[sl]) <= BETA_TOL * s[sl])
+        assert np.all(np.abs(_np(gy) - by[sl]) <= BETA_TOL * s[sl])
+        assert np.count_nonzero(_np(gb) != b[sl]) <= 1
 
 
 def test_expansion_large_config(torch):
@@ -542,25 +568,29 @@ def test_expansion_precision_study_full_lattice(torch):
         assert frac <= MISBIN_FP64
 
 
-def test_expansion_dense_cluster_falls_back(torch):
-    """More near stars than the per-tile lists hold (3000 stars within 0.3 of
-    the lattice centre): those tiles sum every star directly; the result
-    still matches the oracle ray by ray."""
+@pytest.mark.parametrize("block", [1, 2, 4])
+def test_expansion_dense_cluster_falls_back(torch, block):
+    """More near stars than the lists hold (3000 stars within 0.3 of the
+    lattice centre): those blocks sum every star directly; the result still
+    matches the oracle ray by ray.  With a cluster off to one side, other
+    blocks of the same lattice take the expansion path."""
     rng = np.random.default_rng(22)
     r = 0.3 * np.sqrt(rng.random(3000))
     phi = 2 * np.pi * rng.random(3000)
     far_r = 20 + 10 * rng.random(500)
     far_p = 2 * np.pi * rng.random(500)
-    xs = np.concatenate([r * np.cos(phi), far_r * np.cos(far_p)])
-    ys = np.concatenate([r * np.sin(phi), far_r * np.sin(far_p)])
-    ms = rng.uniform(0.001, 0.002, 3500)
-    lens = (0.1, 0.1, 0.0, xs, ys, ms)
-    rays = (-1.0, -1.0, 2 / 192, 2 / 192, 192, 192, 0, 0)
-    pix = (-1.0, -1.0, 2 / 64, 2 / 64, 64, 64)
-    ox, oy, ob = ora.shoot(lens, rays, pix)
-    s = ora.error_scale_block(lens, rays)
-    with R.Context(lens) as ctx:
-        gx, gy, gb = ctx.shoot(rays, "fp64_expansion", pix)
-        assert np.all(np.abs(_np(gx) - ox) <= BETA_TOL * s)
-        assert np.all(np.abs(_np(gy) - oy) <= BETA_TOL * s)
-        assert np.count_nonzero(_np(gb) != ob) <= 1
+    for shift in (0.0, 1.6):
+        xs = np.concatenate([r * np.cos(phi) + shift, far_r * np.cos(far_p)])
+        ys = np.concatenate([r * np.sin(phi), far_r * np.sin(far_p)])
+        ms = rng.uniform(0.001, 0.002, 3500)
+        lens = (0.1, 0.1, 0.0, xs, ys, ms)
+        rays = (-2.0, -2.0, 4 / 512, 4 / 512, 512, 512, 0, 0)
+        pix = (-1.0, -1.0, 2 / 64, 2 / 64, 64, 64)
+        ox, oy, ob = ora.shoot(lens, rays, pix)
+        s = ora.error_scale_block(lens, rays)
+        with R.Context(lens) as ctx:
+            ctx.set_expansion_block(block)
+            gx, gy, gb = ctx.shoot(rays, "fp64_expansion", pix)
+            assert np.all(np.abs(_np(gx) - ox) <= BETA_TOL * s), shift
+            assert np.all(np.abs(_np(gy) - oy) <= BETA_TOL * s), shift
+            assert np.count_nonzero(_np(gb) != ob) <= 1
