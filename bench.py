@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-expansion", action="store_true", help="skip the far-field expansion study")
     ap.add_argument("--no-light-curves", action="store_true", help="skip the light-curve timing")
     ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
+    ap.add_argument("--cpu-all-rays", type=int, default=2048,
+                    help="side of the ray sample of the all-cores oracle run")
     ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
     ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -258,6 +260,39 @@ def cpu_baseline(w, side):
                       f"({inter:.3e} interactions, {dt:.1f} s, single thread)"}
 
 
+def _oracle_band(job):
+    from oracle import shooter as ora
+    lens, rays, pix = job
+    ora.map_counts(lens, rays, pix)
+    return rays[5]
+
+
+def _ready(_):
+    return os.getpid()
+
+
+def cpu_parallel_baseline(w, side, procs):
+    """The oracle as it stands, run as `procs` independent processes on
+    disjoint row bands of the central side x side rays (band additivity makes
+    the bands' maps add up to the block's map exactly).  Runs before the GPU
+    is touched, so the workers are plain forks of a CPU-only process."""
+    import multiprocessing as mp
+    blk = w.rays.block((w.rays.nx - side) // 2, (w.rays.ny - side) // 2, side, side)
+    edges = [side * k // procs for k in range(procs + 1)]
+    jobs = [(w.lens.as_tuple(), blk.block(0, edges[k], side, edges[k + 1] - edges[k]).as_tuple(),
+             w.pix.as_tuple()) for k in range(procs)]
+    with mp.get_context("fork").Pool(procs) as pool:
+        pool.map(_ready, range(procs), chunksize=1)   # workers are up before the clock starts
+        t0 = time.perf_counter()
+        done = pool.map(_oracle_band, jobs, chunksize=1)
+        dt = time.perf_counter() - t0
+    assert sum(done) == side
+    inter = side * side * w.lens.n_stars
+    return {"value": inter / dt, "unit": "interactions/s", "cores": procs, "kind": "oracle",
+            "sample": f"central {side}x{side} rays of the 8192^2 lattice x {w.lens.n_stars} stars in "
+                      f"{procs} row bands, one process each ({inter:.3e} interactions, {dt:.1f} s)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -267,6 +302,12 @@ def main():
     import torch
     from paper_1703_09707_amd import raysh
     from paper_1703_09707_amd import workloads as W
+
+    cpu_all = None
+    if not args.no_cpu:   # before anything initialises the GPU: the pool forks this process
+        procs = max(1, min(16, os.cpu_count() or 1))
+        print(f"# cpu baseline, all cores ({procs} processes)", file=sys.stderr, flush=True)
+        cpu_all = cpu_parallel_baseline(W.plain_fp64_large(), args.cpu_all_rays, procs)
 
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
@@ -338,6 +379,23 @@ def main():
             "misbinned_fraction_lower_bound": 0.5 * (l1 + dn) / w.rays.n_rays,
             "tile": list(ctx.get_tile("fp32_bulk"))}
     ctx.close()
+    del counts
+    # end to end, as the paper times a map: context and star upload, one map,
+    # the map back on the host
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = raysh.Context(w.lens, device=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    m = ctx.map(w.rays, w.pix, "fp64")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    host_map = m.cpu()
+    t3 = time.perf_counter()
+    ctx.close()
+    out["end_to_end_ms"] = {"init_and_star_upload": 1e3 * (t1 - t0), "map": 1e3 * (t2 - t1),
+                            "map_to_host": 1e3 * (t3 - t2), "total": 1e3 * (t3 - t0)}
+    del m, host_map
     if not args.no_batch:
         print("# batch (64 sets)", file=sys.stderr, flush=True)
         out["batch"] = batch_section(torch, raysh, W)
@@ -357,6 +415,7 @@ def main():
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)
+        out["cpu_baseline_all_cores"] = cpu_all
     print(json.dumps(out), flush=True)
 
 

@@ -62,21 +62,23 @@ enum {
     RAYSH_FP32_BULK = 1,     /* star terms in FP32 on tile-relative coordinates,
                                 flushed into FP64 sums; theta, the macro term and
                                 the beta -> pixel step stay FP64 */
-    RAYSH_FP64_EXPANSION = 2 /* FP64; for each 64 x 64 ray tile, the stars farther
-                                than rho / theta_open from the tile centre (rho:
-                                the tile's radius) enter through one local Taylor
-                                expansion of their summed term (order
-                                raysh_expansion_order()), built once per block of
-                                tiles and re-centred on each tile (see
-                                raysh_set_expansion_block), the others directly;
-                                truncation error below theta_open^(order+1) *
+    RAYSH_FP64_EXPANSION = 2 /* FP64; the stars far from a region of rays (farther
+                                than rho / theta_open from its centre, rho its
+                                radius) enter through one local Taylor expansion
+                                of their summed term (order
+                                raysh_expansion_order()), the others directly.
+                                Regions are blocks of 64 x 64 ray tiles, whose
+                                expansion is re-centred on each tile, and the
+                                tiles themselves, which re-test only the block's
+                                near stars (raysh_set_expansion_block).
+                                Truncation error below theta_open^(order+1) *
                                 (1 + theta_open) / (1 - theta_open) of each far
                                 star's m_k / |theta - theta_k| (1.5e-15 at the
                                 default theta_open = 0.25, 1.6e-13 at the
-                                largest allowed, 0.3).  The
-                                paper names tree codes as the way to avoid the
-                                brute-force sum (Sec. 1); this is their
-                                single-level, per-tile form. */
+                                largest allowed, 0.3).  The paper names tree
+                                codes as the way to avoid the brute-force sum
+                                (Sec. 1); this is a two-level form on the ray
+                                side. */
 };
 
 /* The lens of Eq. (1): smooth convergence, external shear and the stars.

@@ -77,6 +77,45 @@ int launch(raysh_ctx *c, const ShootParams &p, int precision, const char *what) 
     return RAYSH_OK;
 }
 
+// Star records go to the device through two pinned staging buffers of
+// kUploadChunk records, packed on the host while the other one is copied,
+// so the host holds 2 x 16 MiB at any N* instead of a second copy of the
+// star field.  Synchronous: returns when every record is on the device.
+constexpr size_t kUploadChunk = size_t(1) << 19;
+
+hipError_t upload_stars(raysh_ctx *c, const raysh_lens *lens, size_t total) {
+    const size_t per = std::min(kUploadChunk, total);
+    const int n_buf = total > per ? 2 : 1;
+    Star *stage[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < n_buf && e == hipSuccess; ++b) {
+        e = hipHostMalloc((void **)&stage[b], per * sizeof(Star), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done[b], hipEventDisableTiming);
+    }
+    for (size_t off = 0, b = 0; off < total && e == hipSuccess; off += per, b = (b + 1) % n_buf) {
+        const size_t cnt = std::min(per, total - off);
+        if (pending[b]) e = hipEventSynchronize(done[b]);   // the buffer's last copy has finished
+        if (e != hipSuccess) break;
+        for (size_t k = 0; k < cnt; ++k) {
+            const size_t i = off + k;
+            stage[b][k] = (int64_t)i < lens->n_stars ? Star{lens->x[i], lens->y[i], lens->m[i], 0.0}
+                                                      : Star{0.0, 0.0, 0.0, 0.0};
+        }
+        e = hipMemcpyAsync(c->d_stars + off, stage[b], cnt * sizeof(Star), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(done[b], c->stream);
+        pending[b] = e == hipSuccess;
+    }
+    const hipError_t s = hipStreamSynchronize(c->stream);   // also before the buffers are freed
+    if (e == hipSuccess) e = s;
+    for (int b = 0; b < 2; ++b) {
+        if (done[b]) (void)hipEventDestroy(done[b]);
+        if (stage[b]) (void)hipHostFree(stage[b]);
+    }
+    return e;
+}
+
 }  // namespace
 
 int set_error(int code, const char *fmt, ...) {
@@ -235,21 +274,16 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
         c->n_cu = 1;
     }
 
-    std::vector<Star> host((size_t)(n > 0 ? n : 1), Star{0, 0, 0, 0});
-    for (int64_t k = 0; k < n; ++k) host[(size_t)k] = Star{lens->x[k], lens->y[k], lens->m[k], 0.0};
-    e = hipMalloc(&c->d_stars, host.size() * sizeof(Star));
+    const size_t total = (size_t)(n > 0 ? n : 1);   // one zero record when there are no stars
+    e = hipMalloc(&c->d_stars, total * sizeof(Star));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete c;
-        return set_error(RAYSH_ENOMEM, "device allocation of %zu stars failed", host.size());
+        return set_error(RAYSH_ENOMEM, "device allocation of %zu stars failed", total);
     }
     e = hipMalloc(&c->d_counter, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipHostMalloc(&c->h_counter, sizeof(unsigned long long), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->d_stars, host.data(), host.size() * sizeof(Star), hipMemcpyHostToDevice,
-                           c->stream);
-    // the host staging vector dies with this call
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = upload_stars(c, lens, total);
     if (e != hipSuccess) {
         int code = hip_error(e, "raysh_init");
         raysh_free(c);

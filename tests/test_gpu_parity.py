@@ -594,3 +594,23 @@ def test_expansion_dense_cluster_falls_back(torch, block):
             assert np.all(np.abs(_np(gx) - ox) <= BETA_TOL * s), shift
             assert np.all(np.abs(_np(gy) - oy) <= BETA_TOL * s), shift
             assert np.count_nonzero(_np(gb) != ob) <= 1
+
+
+@pytest.mark.parametrize("n_stars", [(1 << 19) - 1, 1 << 19, (1 << 19) + 1, 3 * (1 << 19) + 7])
+def test_star_upload_chunk_boundaries(torch, n_stars):
+    """Star fields around and across the upload's staging chunks (2^19
+    records): every star reaches the device (8 x 8 rays against the oracle)."""
+    rng = np.random.default_rng(n_stars)
+    xs, ys = rng.uniform(-300, 300, n_stars), rng.uniform(-300, 300, n_stars)
+    ms = rng.uniform(0.1, 1.0, n_stars)
+    lens = (0.05, 0.1, 0.02, xs, ys, ms)
+    rays = (-0.5, -0.5, 1 / 8, 1 / 8, 8, 8, 0, 0)
+    pix = (-2.0, -2.0, 0.25, 0.25, 16, 16)
+    ox, oy, ob = ora.shoot(lens, rays, pix)
+    s = ora.error_scale_block(lens, rays)
+    with R.Context(lens) as ctx:
+        assert R.load().raysh_n_stars(ctx.handle) == n_stars
+        gx, gy, gb = ctx.shoot(rays, "fp64", pix)
+        assert np.all(np.abs(_np(gx) - ox) <= BETA_TOL * s)
+        assert np.all(np.abs(_np(gy) - oy) <= BETA_TOL * s)
+        assert np.count_nonzero(_np(gb) != ob) == 0
