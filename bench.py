@@ -207,10 +207,11 @@ def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup):
 
 def light_curve_section(torch, raysh, W, steps):
     """Light curves: the map of the large configuration seen by a Gaussian
-    source of 2 pixels, then 2^20 straight tracks of 256 samples across it.
-    The light-curve kernel is a gather bound by HBM: its algorithmic bytes
-    are the curves written, the track end points read and the source map
-    read once."""
+    source of 2 pixels, then 2^20 straight tracks of 256 samples across it,
+    visited in the library's track order (sorted once per track set).  The
+    light-curve kernel is a gather bound by HBM: its algorithmic bytes are
+    the curves written, the track end points read and the source map read
+    once."""
     lw = W.light_curves_large()
     w = lw.maps
     norm = (w.rays.dx * w.rays.dy) / (w.pix.Px * w.pix.Py)
@@ -221,29 +222,38 @@ def light_curve_section(torch, raysh, W, steps):
     mu, grid = raysh.source_map(counts, w.pix, norm, lw.profile, lw.size)
     tracks = [torch.from_numpy(a).cuda() for a in W.light_curve_tracks(grid, lw.n_tracks, lw.length)]
     curves = torch.empty((lw.n_tracks, lw.n_samples), dtype=torch.float64, device="cuda")
-    raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves)
+    order = raysh.track_order(grid, *tracks)
+    raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves, order=order)
     torch.cuda.synchronize()
-    sm, lc = [], []
+    sm, so, lc, lu = [], [], [], []
     for _ in range(steps):
-        a, b, c = ev(), ev(), ev()
+        a, b, c, d, e = ev(), ev(), ev(), ev(), ev()
         a.record(stream)
         mu, grid = raysh.source_map(counts, w.pix, norm, lw.profile, lw.size)
         b.record(stream)
-        raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves)
+        order = raysh.track_order(grid, *tracks)
         c.record(stream)
+        raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves, order=order)
+        d.record(stream)
+        raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves)
+        e.record(stream)
         torch.cuda.synchronize()
         sm.append(a.elapsed_time(b))
-        lc.append(b.elapsed_time(c))
+        so.append(b.elapsed_time(c))
+        lc.append(c.elapsed_time(d))
+        lu.append(d.elapsed_time(e))
     lc_ms = sum(lc) / len(lc)
     samples = lw.n_tracks * lw.n_samples
-    nbytes = samples * 8 + lw.n_tracks * 32 + mu.numel() * 8
+    nbytes = samples * 8 + lw.n_tracks * (32 + 4) + mu.numel() * 8
     achieved = nbytes / (lc_ms * 1e-3) / 1e9
     return {"workload": lw.name, "samples": samples,
             "source_map_ms": sum(sm) / len(sm),
+            "track_order_ms": sum(so) / len(so),
             "light_curve_kernel_ms": lc_ms,
+            "light_curve_kernel_ms_given_order": sum(lu) / len(lu),
             "samples_per_s": samples / (lc_ms * 1e-3),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "kernel": "light_curve_kernel",
+                         "frac": achieved / HBM_PEAK_GBS, "kernel": "light_curve_track_kernel",
                          "bytes_per_launch": nbytes}}
 
 

@@ -350,15 +350,43 @@ int raysh_source_map(const int32_t *counts, int32_t nx, int32_t ny, double norm,
  *          interpolation of its four surrounding centres (i = min(floor(u),
  *          nx - 2), fx = u - i, r0 = m[j][i] + fx (m[j][i+1] - m[j][i]),
  *          r1 likewise on row j+1, value r0 + fy (r1 - r0)); any other
- *          sample is NaN.  Every product and sum is rounded on its own.
+ *          sample is NaN.  Every product and sum is rounded on its own;
+ *   order: NULL (tracks in the order given) or device int32[n_tracks], a
+ *          permutation of the tracks in which to visit them (as written by
+ *          raysh_track_order).  The curves are the same either way: row t
+ *          of curves is track t.  Entries outside [0, n_tracks) are skipped.
  * Asynchronous on hip_stream, on mu_s's device.  n_tracks == 0 is a no-op.
  * EINVAL on a bad grid, n_tracks < 0, n_samples outside [1, 2^24], NULL or
  * non-device buffers; EOVERFLOW above 2^31-1 map pixels or (2^31-1) * 256
  * samples.
  */
 int raysh_light_curves(const double *mu_s, const raysh_pixels *grid, int64_t n_tracks, int32_t n_samples,
-                       const double *xa, const double *ya, const double *xb, const double *yb, double *curves,
-                       void *hip_stream);
+                       const double *xa, const double *ya, const double *xb, const double *yb,
+                       const int32_t *order, double *curves, void *hip_stream);
+
+/* Device workspace, in bytes, that raysh_track_order needs for a source map
+ * of pixel grid `grid` (0 for an invalid grid). */
+size_t raysh_track_order_workspace(const raysh_pixels *grid);
+
+/*
+ * raysh_track_order: a visiting order for raysh_light_curves in which tracks
+ * that run together read neighbouring parts of the source map: the tracks
+ * sorted by the cell (16 x 16 pixels of grid, larger for maps of more than
+ * 2048 cells a side) holding the midpoint of their end points, cells in Z
+ * (Morton) order; midpoints outside the map go to the nearest edge cell.  The
+ * order of tracks within a cell is unspecified.
+ *   xa, ya, xb, yb: device FP64 arrays of n_tracks end points (as for
+ *                   raysh_light_curves);
+ *   order:          device int32[n_tracks], overwritten with a permutation
+ *                   of 0 .. n_tracks - 1;
+ *   workspace:      device memory of raysh_track_order_workspace(grid) bytes.
+ * Asynchronous on hip_stream, on xa's device.  n_tracks == 0 is a no-op.
+ * EINVAL on a bad grid, n_tracks < 0, NULL or non-device buffers or a short
+ * workspace; EOVERFLOW above 2^31-1 tracks.
+ */
+int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, const double *xa, const double *ya,
+                      const double *xb, const double *yb, void *workspace, size_t workspace_bytes, int32_t *order,
+                      void *hip_stream);
 
 /*
  * The network: layers n_in -> n_hidden -> n_hidden -> n_out, GELU (erf

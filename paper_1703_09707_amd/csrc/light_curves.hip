@@ -21,6 +21,7 @@
 // a wave's reads fall on a few neighbouring rows of the map, which stays in
 // L2 (a 1024^2 FP64 map is 8 MiB).  Its HBM traffic is the curves written
 // plus the map read once.
+#include <algorithm>
 #include <cmath>
 #include <limits>
 #include <vector>
@@ -109,8 +110,8 @@ constexpr int kSpt = 4;
 __global__ __launch_bounds__(kLcThreads) void light_curve_kernel(
     const double *__restrict__ mu, int nx, int ny, double x0, double y0, double ipx, double ipy,
     const double *__restrict__ xa, const double *__restrict__ ya, const double *__restrict__ xb,
-    const double *__restrict__ yb, int64_t n_tracks, int n_samples, float inv_nf, double inv_n1,
-    double *__restrict__ out) {
+    const double *__restrict__ yb, const int32_t *__restrict__ order, int64_t n_tracks, int n_samples,
+    float inv_nf, double inv_n1, double *__restrict__ out) {
 #pragma clang fp contract(off)
     const int64_t base = (int64_t)blockIdx.x * (kSpt * kLcThreads);
     const int64_t total = n_tracks * (int64_t)n_samples;
@@ -132,7 +133,12 @@ __global__ __launch_bounds__(kLcThreads) void light_curve_kernel(
             kk -= n_samples;
         }
         live[e] = base + threadIdx.x + e * kLcThreads < total;
-        t[e] = live[e] ? t0 + q : 0;   // a finished lane reads track 0 and stores nothing
+        int64_t tt = t0 + q;
+        if (order && live[e]) {
+            tt = order[tt];
+            live[e] = tt >= 0 && tt < n_tracks;   // entries outside the tracks are skipped
+        }
+        t[e] = live[e] ? tt : 0;   // a lane with nothing to do reads track 0 and stores nothing
         k[e] = kk;
     }
     double ax[kSpt], ay[kSpt], bx[kSpt], by[kSpt];
@@ -171,8 +177,184 @@ __global__ __launch_bounds__(kLcThreads) void light_curve_kernel(
         const double r0v = m00[e] + fx[e] * (m01[e] - m00[e]);
         const double r1v = m10[e] + fx[e] * (m11[e] - m10[e]);
         const double val = r0v + fy[e] * (r1v - r0v);
-        if (live[e]) out[base + threadIdx.x + e * kLcThreads] = inside[e] ? val : __builtin_nan("");
+        if (live[e]) out[t[e] * n_samples + k[e]] = inside[e] ? val : __builtin_nan("");
     }
+}
+
+// Tracks of at least kWaveChunk / kSpt samples: each wave takes kWaveChunk
+// consecutive samples of one track, so the track's end points are uniform
+// (scalar loads) and its set-up in centre-index space is done once per
+// wave; each lane then takes kSpt samples, 64 apart, and every store of the
+// wave is 64 consecutive values.  The arithmetic of a sample is the same as
+// light_curve_kernel's, operation for operation.
+constexpr int kWaveChunk = 64 * kSpt;
+typedef const __attribute__((address_space(4))) double ConstDouble;
+
+// A value every lane of the wave holds alike, in scalar registers.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__global__ __launch_bounds__(kLcThreads) void light_curve_track_kernel(
+    const double *__restrict__ mu, int nx, int ny, double x0, double y0, double ipx, double ipy,
+    const double *__restrict__ xa, const double *__restrict__ ya, const double *__restrict__ xb,
+    const double *__restrict__ yb, const int32_t *__restrict__ order, int64_t n_tracks, int64_t n_chunks,
+    int chunks_per_track, int n_samples, double inv_n1, double *__restrict__ out) {
+#pragma clang fp contract(off)
+    const int64_t chunk = wave_uniform((int64_t)blockIdx.x * (kLcThreads / 64) + threadIdx.x / 64);
+    if (chunk >= n_chunks) return;   // uniform in the wave
+    const int64_t tp = chunk / chunks_per_track;
+    const int k0 = (int)(chunk - tp * chunks_per_track) * kWaveChunk;
+    int64_t t = tp;
+    if (order) {
+        t = ((const __attribute__((address_space(4))) int32_t *)order)[tp];
+        if (t < 0 || t >= n_tracks) return;   // uniform: entries outside the tracks are skipped
+    }
+    const int lane = threadIdx.x % 64;
+    const ConstDouble *cxa = (const ConstDouble *)xa, *cya = (const ConstDouble *)ya;
+    const ConstDouble *cxb = (const ConstDouble *)xb, *cyb = (const ConstDouble *)yb;
+    const double ax = cxa[t], ay = cya[t];
+    const double ua = (ax - x0) * ipx - 0.5;
+    const double va = (ay - y0) * ipy - 0.5;
+    const double du = ((cxb[t] - ax) * ipx) * inv_n1;
+    const double dv = ((cyb[t] - ay) * ipy) * inv_n1;
+    double fx[kSpt], fy[kSpt], m00[kSpt], m01[kSpt], m10[kSpt], m11[kSpt];
+    bool inside[kSpt];
+#pragma unroll
+    for (int e = 0; e < kSpt; ++e) {
+        const int k = k0 + lane + 64 * e;
+        const double u = ua + du * (double)k;
+        const double v = va + dv * (double)k;
+        inside[e] = (u >= 0.0) & (u <= (double)(nx - 1)) & (v >= 0.0) & (v <= (double)(ny - 1));
+        const double uc = inside[e] ? u : 0.0;   // in [0, nx - 1]: the conversion is defined
+        const double vc = inside[e] ? v : 0.0;
+        const int i = min((int)uc, nx - 2);      // uc >= 0: truncation is floor
+        const int j = min((int)vc, ny - 2);
+        fx[e] = uc - (double)i;
+        fy[e] = vc - (double)j;
+        const double *p = mu + (int64_t)j * nx + i;
+        m00[e] = p[0];
+        m01[e] = p[1];
+        m10[e] = p[nx];
+        m11[e] = p[nx + 1];
+    }
+    double *row = out + t * n_samples;
+#pragma unroll
+    for (int e = 0; e < kSpt; ++e) {
+        const int k = k0 + lane + 64 * e;
+        const double r0v = m00[e] + fx[e] * (m01[e] - m00[e]);
+        const double r1v = m10[e] + fx[e] * (m11[e] - m10[e]);
+        const double val = r0v + fy[e] * (r1v - r0v);
+        if (k < n_samples) row[k] = inside[e] ? val : __builtin_nan("");
+    }
+}
+
+// --- track order: a counting sort of the tracks by the cell holding their
+// midpoint, cells of kCellPx x kCellPx pixels (larger for maps of more than
+// 2048 cells a side) numbered in Z (Morton) order, so that tracks that run
+// together on the GPU read neighbouring parts of the map.
+constexpr int kCellPx = 16;
+constexpr int kMaxCellsPerSide = 2048;
+constexpr int kScanThreads = 1024;
+
+struct CellGrid {
+    double x0, y0, ipx, ipy;   // map origin and inverse pixel size
+    int cell_px;               // pixels per cell side
+    int cells_x, cells_y;
+    int side;                  // power of two >= cells_x, cells_y
+};
+
+CellGrid cell_grid(const raysh_pixels *g) {
+    CellGrid c{};
+    c.x0 = g->x0;
+    c.y0 = g->y0;
+    c.ipx = 1.0 / g->px;
+    c.ipy = 1.0 / g->py;
+    c.cell_px = kCellPx;
+    while ((std::max(g->nx, g->ny) + c.cell_px - 1) / c.cell_px > kMaxCellsPerSide) c.cell_px *= 2;
+    c.cells_x = (g->nx + c.cell_px - 1) / c.cell_px;
+    c.cells_y = (g->ny + c.cell_px - 1) / c.cell_px;
+    c.side = 1;
+    while (c.side < c.cells_x || c.side < c.cells_y) c.side *= 2;
+    return c;
+}
+
+__device__ __forceinline__ int cell_of(double coord, int cells) {
+    // coord in cells; NaN and values below 0 go to cell 0, values beyond the map to the last cell
+    if (!(coord >= 0.0)) return 0;
+    if (coord >= (double)cells) return cells - 1;
+    return (int)coord;
+}
+
+__device__ __forceinline__ uint32_t morton(uint32_t x, uint32_t y) {
+    uint32_t key = 0;
+    for (int b = 0; b < 12; ++b) key |= ((x >> b) & 1u) << (2 * b) | ((y >> b) & 1u) << (2 * b + 1);
+    return key;
+}
+
+// The counting and the scattering pass must agree on every key: the same
+// operations, none contracted.
+__device__ __forceinline__ uint32_t track_key(const CellGrid &c, double xa, double ya, double xb, double yb) {
+#pragma clang fp contract(off)
+    const double mx = 0.5 * (xa + xb), my = 0.5 * (ya + yb);
+    const int cx = cell_of(((mx - c.x0) * c.ipx) / (double)c.cell_px, c.cells_x);
+    const int cy = cell_of(((my - c.y0) * c.ipy) / (double)c.cell_px, c.cells_y);
+    return morton((uint32_t)cx, (uint32_t)cy);
+}
+
+__global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(kLcThreads) void track_count_kernel(CellGrid c, const double *xa, const double *ya,
+                                                                 const double *xb, const double *yb,
+                                                                 int64_t n_tracks, uint32_t *counts) {
+    const int64_t t = (int64_t)blockIdx.x * kLcThreads + threadIdx.x;
+    if (t >= n_tracks) return;
+    atomicAdd(&counts[track_key(c, xa[t], ya[t], xb[t], yb[t])], 1u);
+}
+
+// Exclusive prefix sum of counts[0, n) in place (one workgroup): each thread
+// sums a contiguous run, the runs' sums are scanned in LDS, then each thread
+// rewrites its run.
+__global__ __launch_bounds__(kScanThreads) void track_scan_kernel(uint32_t *counts, int64_t n) {
+    __shared__ uint32_t part[kScanThreads];
+    const int64_t per = (n + kScanThreads - 1) / kScanThreads;
+    const int64_t lo = std::min<int64_t>((int64_t)threadIdx.x * per, n);
+    const int64_t hi = std::min<int64_t>(lo + per, n);
+    uint32_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += counts[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < kScanThreads; ++i) {
+            const uint32_t v = part[i];
+            part[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    uint32_t run = part[threadIdx.x];
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint32_t v = counts[i];
+        counts[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kLcThreads) void track_scatter_kernel(CellGrid c, const double *xa, const double *ya,
+                                                                   const double *xb, const double *yb,
+                                                                   int64_t n_tracks, uint32_t *offsets,
+                                                                   int32_t *order) {
+    const int64_t t = (int64_t)blockIdx.x * kLcThreads + threadIdx.x;
+    if (t >= n_tracks) return;
+    const uint32_t pos = atomicAdd(&offsets[track_key(c, xa[t], ya[t], xb[t], yb[t])], 1u);
+    order[pos] = (int32_t)t;   // pos < n_tracks: the offsets partition [0, n_tracks)
 }
 
 int check_profile(int profile, double size, double px, double py, int32_t nx, int32_t ny) {
@@ -269,9 +451,60 @@ extern "C" int raysh_source_map(const int32_t *counts, int32_t nx, int32_t ny, d
     return set_ok();
 }
 
+extern "C" size_t raysh_track_order_workspace(const raysh_pixels *grid) {
+    if (!grid || validate_pixels(grid) != RAYSH_OK) return 0;
+    const CellGrid c = cell_grid(grid);
+    return 4 * ((size_t)c.side * (size_t)c.side + 1);
+}
+
+extern "C" int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, const double *xa, const double *ya,
+                                 const double *xb, const double *yb, void *workspace, size_t workspace_bytes,
+                                 int32_t *order, void *hip_stream) {
+    if (!grid) return set_error(RAYSH_EINVAL, "raysh_track_order: grid is NULL");
+    if (int r = validate_pixels(grid)) return r;
+    if (n_tracks < 0) return set_error(RAYSH_EINVAL, "n_tracks < 0");
+    if (n_tracks > std::numeric_limits<int32_t>::max())
+        return set_error(RAYSH_EOVERFLOW, "more than 2^31-1 tracks");
+    if (n_tracks == 0) return set_ok();
+    if (!xa || !ya || !xb || !yb || !order || !workspace) return set_error(RAYSH_EINVAL, "NULL buffer");
+    const size_t need = raysh_track_order_workspace(grid);
+    if (workspace_bytes < need)
+        return set_error(RAYSH_EINVAL, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, xa) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(RAYSH_EINVAL, "xa is not device memory");
+    }
+    const int device = attr.device;
+    DeviceGuard g(device);
+    if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", device);
+    const size_t tb = (size_t)n_tracks * 8;
+    if (int r = validate_device_ptr(xa, tb, device, "xa")) return r;
+    if (int r = validate_device_ptr(ya, tb, device, "ya")) return r;
+    if (int r = validate_device_ptr(xb, tb, device, "xb")) return r;
+    if (int r = validate_device_ptr(yb, tb, device, "yb")) return r;
+    if (int r = validate_device_ptr(order, (size_t)n_tracks * 4, device, "order")) return r;
+    if (int r = validate_device_ptr(workspace, need, device, "workspace")) return r;
+
+    hipStream_t s = (hipStream_t)hip_stream;
+    const CellGrid c = cell_grid(grid);
+    const int64_t n_keys = (int64_t)c.side * c.side;
+    uint32_t *counts = (uint32_t *)workspace;
+    const unsigned tb_blocks = (unsigned)((n_tracks + kLcThreads - 1) / kLcThreads);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n_keys + 255) / 256)), dim3(256), 0, s, counts, n_keys);
+    hipLaunchKernelGGL(track_count_kernel, dim3(tb_blocks), dim3(kLcThreads), 0, s, c, xa, ya, xb, yb, n_tracks,
+                       counts);
+    hipLaunchKernelGGL(track_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, n_keys);
+    hipLaunchKernelGGL(track_scatter_kernel, dim3(tb_blocks), dim3(kLcThreads), 0, s, c, xa, ya, xb, yb, n_tracks,
+                       counts, order);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "raysh_track_order");
+    return set_ok();
+}
+
 extern "C" int raysh_light_curves(const double *mu_s, const raysh_pixels *grid, int64_t n_tracks,
                                   int32_t n_samples, const double *xa, const double *ya, const double *xb,
-                                  const double *yb, double *curves, void *hip_stream) {
+                                  const double *yb, const int32_t *order, double *curves, void *hip_stream) {
     if (!grid) return set_error(RAYSH_EINVAL, "raysh_light_curves: grid is NULL");
     if (int r = validate_pixels(grid)) return r;
     if (grid->nx < 2 || grid->ny < 2) return set_error(RAYSH_EINVAL, "the source map needs at least 2 x 2 pixels");
@@ -301,13 +534,29 @@ extern "C" int raysh_light_curves(const double *mu_s, const raysh_pixels *grid, 
     if (int r = validate_device_ptr(yb, tb, device, "yb")) return r;
     const int64_t total = n_tracks * (int64_t)n_samples;
     if (int r = validate_device_ptr(curves, (size_t)total * 8, device, "curves")) return r;
+    if (order)
+        if (int r = validate_device_ptr(order, (size_t)n_tracks * 4, device, "order")) return r;
 
     hipStream_t s = (hipStream_t)hip_stream;
-    const float inv_nf = 1.0f / (float)n_samples;                       // n_samples <= 2^24: exact in float
     const double inv_n1 = n_samples > 1 ? 1.0 / (double)(n_samples - 1) : 0.0;
-    hipLaunchKernelGGL(light_curve_kernel, dim3((unsigned)((total + kSpt * kLcThreads - 1) / (kSpt * kLcThreads))),
-                       dim3(kLcThreads), 0, s, mu_s, grid->nx, grid->ny, grid->x0, grid->y0, 1.0 / grid->px,
-                       1.0 / grid->py, xa, ya, xb, yb, n_tracks, n_samples, inv_nf, inv_n1, curves);
+    if (n_samples >= kWaveChunk / kSpt) {
+        // one wave per kWaveChunk samples of a track
+        const int chunks_per_track = (n_samples + kWaveChunk - 1) / kWaveChunk;
+        const int64_t n_chunks = n_tracks * chunks_per_track;
+        const int64_t waves_per_block = kLcThreads / 64;
+        if ((n_chunks + waves_per_block - 1) / waves_per_block > std::numeric_limits<int32_t>::max())
+            return set_error(RAYSH_EOVERFLOW, "more than 2^31-1 workgroups of tracks");
+        hipLaunchKernelGGL(light_curve_track_kernel,
+                           dim3((unsigned)((n_chunks + waves_per_block - 1) / waves_per_block)), dim3(kLcThreads), 0,
+                           s, mu_s, grid->nx, grid->ny, grid->x0, grid->y0, 1.0 / grid->px, 1.0 / grid->py, xa, ya, xb,
+                           yb, order, n_tracks, n_chunks, chunks_per_track, n_samples, inv_n1, curves);
+    } else {
+        const float inv_nf = 1.0f / (float)n_samples;                   // n_samples <= 2^24: exact in float
+        hipLaunchKernelGGL(light_curve_kernel,
+                           dim3((unsigned)((total + kSpt * kLcThreads - 1) / (kSpt * kLcThreads))), dim3(kLcThreads),
+                           0, s, mu_s, grid->nx, grid->ny, grid->x0, grid->y0, 1.0 / grid->px, 1.0 / grid->py, xa, ya,
+                           xb, yb, order, n_tracks, n_samples, inv_nf, inv_n1, curves);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "raysh_light_curves");
     return set_ok();

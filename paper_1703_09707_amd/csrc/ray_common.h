@@ -171,6 +171,10 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+__device__ __forceinline__ double uniform_f64(double v) {
+    return __builtin_bit_cast(double, uniform64(__builtin_bit_cast(int64_t, v)));
+}
+
 __device__ __forceinline__ const Star *uniform_ptr(const Star *p) {
     return (const Star *)(uintptr_t)uniform64((int64_t)(uintptr_t)p);
 }

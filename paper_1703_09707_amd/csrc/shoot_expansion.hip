@@ -71,6 +71,10 @@ __device__ __forceinline__ void region(const ShootParams &p, int64_t i, int64_t 
     cy = 0.5 * (y_first + y_last);
     const double hx = 0.5 * (x_last - x_first), hy = 0.5 * (y_last - y_first);
     rho = __builtin_sqrt(hx * hx + hy * hy) * (1.0 + 1e-12) + 1e-290;
+    // the same in every lane: keep them in scalar registers
+    cx = uniform_f64(cx);
+    cy = uniform_f64(cy);
+    rho = uniform_f64(rho);
 }
 
 // One pass over `count` stars split into four contiguous quarters, one per
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(kThreads, 2) void expansion_fp64_kernel(ShootParams
     const int64_t b_j = (int64_t)(blockIdx.x / blocks_x) * (kTile * L);
     const ConstStar *st = const_stars(uniform_ptr(p.stars));
     const int n = uniform(p.n_stars);
-    const double inv_theta = 1.0 / theta_open;
+    const double inv_theta = uniform_f64(1.0 / theta_open);
 
     // --- the block: far stars into A, near stars into the outer lists
     double bcx, bcy, brho;
@@ -230,7 +234,8 @@ __global__ __launch_bounds__(kThreads, 2) void expansion_fp64_kernel(ShootParams
 #pragma unroll
         for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
         const double r_near = brho * inv_theta;
-        p2l_pass<false>(st, n, nullptr, nullptr, bcx, bcy, brho, r_near * r_near, acc, ex.outer_idx, ex.outer_n);
+        p2l_pass<false>(st, n, nullptr, nullptr, bcx, bcy, brho, uniform_f64(r_near * r_near), acc, ex.outer_idx,
+                        ex.outer_n);
         reduce_coeffs<false>(acc, ex, ex.A);   // its barriers also publish outer_n
     }
     bool overflow = false;
@@ -262,8 +267,8 @@ __global__ __launch_bounds__(kThreads, 2) void expansion_fp64_kernel(ShootParams
 #pragma unroll
                 for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
                 const double r_near = rho * inv_theta;
-                p2l_pass<true>(st, n_outer, ex.outer_idx, ex.outer_n, cx, cy, rho, r_near * r_near, acc,
-                               ex.inner_idx, ex.inner_n);
+                p2l_pass<true>(st, uniform(n_outer), ex.outer_idx, ex.outer_n, cx, cy, rho,
+                               uniform_f64(r_near * r_near), acc, ex.inner_idx, ex.inner_n);
                 __syncthreads();                        // B is written before it is added to
                 reduce_coeffs<true>(acc, ex, ex.B);     // its barriers also publish inner_n
                 near_idx = ex.inner_idx;

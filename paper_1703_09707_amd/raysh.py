@@ -36,6 +36,7 @@ EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", 
            "raysh_get_tile", "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch",
            "raysh_histogram_workspace", "raysh_log_mag_histogram",
            "raysh_source_map_shape", "raysh_source_map_workspace", "raysh_source_map", "raysh_light_curves",
+           "raysh_track_order_workspace", "raysh_track_order",
            "raysh_mlp_create",
            "raysh_mlp_n_params", "raysh_mlp_get_params", "raysh_mlp_forward", "raysh_mlp_gradient",
            "raysh_mlp_adam_step", "raysh_mlp_train_step", "raysh_mlp_sync", "raysh_mlp_free",
@@ -116,8 +117,12 @@ def load():
     lib.raysh_source_map.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, I, D, D, D, P, ctypes.c_size_t, P, P]
     lib.raysh_source_map.restype = I
     lib.raysh_light_curves.argtypes = [P, ctypes.POINTER(Pixels), ctypes.c_int64, ctypes.c_int32,
-                                       P, P, P, P, P, P]
+                                       P, P, P, P, P, P, P]
     lib.raysh_light_curves.restype = I
+    lib.raysh_track_order_workspace.argtypes = [ctypes.POINTER(Pixels)]
+    lib.raysh_track_order_workspace.restype = ctypes.c_size_t
+    lib.raysh_track_order.argtypes = [ctypes.POINTER(Pixels), ctypes.c_int64, P, P, P, P, P, ctypes.c_size_t, P, P]
+    lib.raysh_track_order.restype = I
     F = ctypes.c_float
     lib.raysh_mlp_create.argtypes = [ctypes.POINTER(P), I, P, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32, P]
@@ -362,19 +367,39 @@ def source_map(counts, pix, norm, profile="gaussian", size=0.05, stream=None):
     return out, grid
 
 
-def light_curves(mu_s, grid, xa, ya, xb, yb, n_samples, out=None, stream=None):
+def track_order(grid, xa, ya, xb, yb, stream=None):
+    """raysh_track_order: a visiting order (int32 device permutation) of the
+    tracks in which neighbouring tracks read neighbouring parts of the map."""
+    torch = _torch()
+    g = pixels_struct(grid)
+    n = int(xa.numel())
+    for a in (xa, ya, xb, yb):
+        assert a.dtype == torch.float64 and a.is_contiguous() and int(a.numel()) == n
+    lib = load()
+    ws = torch.empty(max(1, lib.raysh_track_order_workspace(ctypes.byref(g))), dtype=torch.uint8, device=xa.device)
+    order = torch.empty(n, dtype=torch.int32, device=xa.device)
+    check(lib.raysh_track_order(ctypes.byref(g), n, _ptr(xa), _ptr(ya), _ptr(xb), _ptr(yb), _ptr(ws), ws.numel(),
+                                _ptr(order), _stream_handle(torch, xa.device, stream)))
+    return order
+
+
+def light_curves(mu_s, grid, xa, ya, xb, yb, n_samples, out=None, order=None, stream=None):
     """raysh_light_curves: tracks (xa, ya) -> (xb, yb) (FP64 device arrays)
     sampled at n_samples points across the source map mu_s of pixel grid
-    `grid`.  Returns FP64 (n_tracks, n_samples), NaN outside the map."""
+    `grid`, visited in `order` when given (see track_order).  Returns FP64
+    (n_tracks, n_samples), NaN outside the map; row t is track t."""
     torch = _torch()
     g = pixels_struct(grid)
     n = int(xa.numel())
     for a in (mu_s, xa, ya, xb, yb):
         assert a.dtype == torch.float64 and a.is_contiguous()
     assert tuple(mu_s.shape) == (g.ny, g.nx) and all(int(a.numel()) == n for a in (ya, xb, yb))
+    if order is not None:
+        assert order.dtype == torch.int32 and order.is_contiguous() and int(order.numel()) == n
     if out is None:
         out = torch.empty((n, int(n_samples)), dtype=torch.float64, device=mu_s.device)
     assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == n * int(n_samples)
     check(load().raysh_light_curves(_ptr(mu_s), ctypes.byref(g), n, int(n_samples), _ptr(xa), _ptr(ya),
-                                    _ptr(xb), _ptr(yb), _ptr(out), _stream_handle(torch, mu_s.device, stream)))
+                                    _ptr(xb), _ptr(yb), _ptr(order), _ptr(out),
+                                    _stream_handle(torch, mu_s.device, stream)))
     return out

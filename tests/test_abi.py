@@ -233,12 +233,27 @@ def test_source_map_and_light_curve_argument_errors(lib):
     assert "workspace" in _err(lib)
     lc = lib.raysh_light_curves
     g = R.Pixels(0.0, 0.0, 0.1, 0.1, 16, 16)
-    assert lc(dummy, None, 4, 8, dummy, dummy, dummy, dummy, dummy, None) == R.EINVAL
-    assert lc(dummy, ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 1, 16)), 4, 8, dummy, dummy, dummy, dummy, dummy,
-              None) == R.EINVAL
-    assert lc(dummy, ctypes.byref(g), -1, 8, dummy, dummy, dummy, dummy, dummy, None) == R.EINVAL
-    assert lc(dummy, ctypes.byref(g), 4, 0, dummy, dummy, dummy, dummy, dummy, None) == R.EINVAL
-    assert lc(dummy, ctypes.byref(g), 4, (1 << 24) + 1, dummy, dummy, dummy, dummy, dummy, None) == R.EINVAL
-    assert lc(dummy, ctypes.byref(g), 1 << 40, 1 << 20, dummy, dummy, dummy, dummy, dummy, None) == R.EOVERFLOW
-    assert lc(dummy, ctypes.byref(g), 4, 8, None, dummy, dummy, dummy, dummy, None) == R.EINVAL
-    assert lc(None, ctypes.byref(g), 0, 8, None, None, None, None, None, None) == R.OK   # no tracks: no-op
+    d = dummy
+    assert lc(d, None, 4, 8, d, d, d, d, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 1, 16)), 4, 8, d, d, d, d, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(g), -1, 8, d, d, d, d, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(g), 4, 0, d, d, d, d, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(g), 4, (1 << 24) + 1, d, d, d, d, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(g), 1 << 40, 1 << 20, d, d, d, d, None, d, None) == R.EOVERFLOW
+    assert lc(d, ctypes.byref(g), 4, 8, None, d, d, d, None, d, None) == R.EINVAL
+    assert lc(None, ctypes.byref(g), 0, 8, None, None, None, None, None, None, None) == R.OK   # no tracks: no-op
+    to = lib.raysh_track_order
+    assert lib.raysh_track_order_workspace(None) == 0
+    assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 0, 16))) == 0
+    # 1012 pixels a side: 64 cells of 16 pixels, Morton keys over 64 x 64
+    assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 1012, 1012))) == 4 * (64 * 64 + 1)
+    # 40000 pixels a side: cells grow to 32 pixels (1250 a side), keys over 2048 x 2048
+    assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 40000, 100))) == \
+        4 * (2048 * 2048 + 1)
+    assert to(None, 4, d, d, d, d, d, 1 << 30, d, None) == R.EINVAL
+    assert to(ctypes.byref(g), -1, d, d, d, d, d, 1 << 30, d, None) == R.EINVAL
+    assert to(ctypes.byref(g), 1 << 31, d, d, d, d, d, 1 << 30, d, None) == R.EOVERFLOW
+    assert to(ctypes.byref(g), 4, d, d, d, d, d, 4, d, None) == R.EINVAL
+    assert "workspace" in _err(lib)
+    assert to(ctypes.byref(g), 4, d, None, d, d, d, 1 << 30, d, None) == R.EINVAL
+    assert to(ctypes.byref(g), 0, None, None, None, None, None, 0, None, None) == R.OK

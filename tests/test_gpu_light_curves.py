@@ -62,7 +62,7 @@ def _edge_tracks(grid):
     return tuple(np.array(v, np.float64) for v in zip(*t))
 
 
-@pytest.mark.parametrize("n_samples", [1, 2, 7, 256, 1000])
+@pytest.mark.parametrize("n_samples", [1, 2, 7, 63, 64, 256, 1000])
 def test_light_curves_match_oracle_bit_exact(torch, small_map, n_samples):
     """Given the same source map, the curves are bit-identical to the
     oracle's, NaN pattern included (random and edge tracks, a sample count
@@ -94,7 +94,8 @@ def test_light_curves_large_workload(torch):
     tracks = W.light_curve_tracks(grid, lw.n_tracks, lw.length)
     dev = [torch.from_numpy(a).cuda() for a in tracks]
     _say("light curves (large)")
-    curves = R.light_curves(mu, grid, *dev, lw.n_samples)
+    order = R.track_order(grid, *dev)
+    curves = R.light_curves(mu, grid, *dev, lw.n_samples, order=order)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(curves).all())
     rng = np.random.default_rng(5)
@@ -118,12 +119,56 @@ def test_source_map_and_light_curve_errors(torch, small_map):
     import ctypes
     code = lib.raysh_light_curves(ctypes.c_void_p(mu.data_ptr()), ctypes.byref(g), 4, 8,
                                   host.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(mu.data_ptr()),
-                                  ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(mu.data_ptr()),
+                                  ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(mu.data_ptr()), None,
                                   ctypes.c_void_p(mu.data_ptr()), None)
     assert code == R.EINVAL and "xa" in lib.raysh_last_error().decode()
     tiny = torch.zeros(3, dtype=torch.float64, device="cuda")
     t = ctypes.c_void_p(tiny.data_ptr())
-    code = lib.raysh_light_curves(ctypes.c_void_p(mu.data_ptr()), ctypes.byref(g), 1 << 26, 8, t, t, t, t,
+    code = lib.raysh_light_curves(ctypes.c_void_p(mu.data_ptr()), ctypes.byref(g), 1 << 26, 8, t, t, t, t, None,
                                   ctypes.c_void_p(mu.data_ptr()), None)     # 512 MiB per track array
     assert code == R.EINVAL and "needed" in lib.raysh_last_error().decode()
     assert int(tiny.abs().sum()) == 0
+    n4 = torch.zeros(4, dtype=torch.float64, device="cuda")
+    p4 = ctypes.c_void_p(n4.data_ptr())
+    code = lib.raysh_light_curves(ctypes.c_void_p(mu.data_ptr()), ctypes.byref(g), 4, 8, p4, p4, p4, p4,
+                                  host.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(mu.data_ptr()), None)
+    assert code == R.EINVAL and "order" in lib.raysh_last_error().decode()
+
+
+def test_track_order(torch, small_map):
+    """The order is a permutation that visits tracks region by region
+    (consecutive tracks' midpoints are far closer than in the given order),
+    and the curves do not depend on it, for both kernels (fewer than 64
+    samples: one lane per sample; more: one wave per track chunk)."""
+    w, counts, _, norm = small_map
+    mu, grid = R.source_map(counts, w.pix, norm, "gaussian", 2.0 * w.pix.Px)
+    tracks = W.light_curve_tracks(grid, 20000, 1.0, seed=41)
+    dev = [torch.from_numpy(a).cuda() for a in tracks]
+    order = R.track_order(grid, *dev)
+    o = order.cpu().numpy()
+    assert np.array_equal(np.sort(o), np.arange(len(o)))
+    mx, my = 0.5 * (tracks[0] + tracks[2]), 0.5 * (tracks[1] + tracks[3])
+    step = lambda idx: np.hypot(np.diff(mx[idx]), np.diff(my[idx])).mean()   # noqa: E731
+    _say("mean step between consecutive midpoints: given", step(np.arange(len(o))), "ordered", step(o))
+    assert step(o) < 0.1 * step(np.arange(len(o)))
+    for n_samples in (7, 300):
+        plain = R.light_curves(mu, grid, *dev, n_samples)
+        ordered = R.light_curves(mu, grid, *dev, n_samples, order=order)
+        assert torch.equal(torch.isnan(plain), torch.isnan(ordered))
+        assert torch.equal(torch.nan_to_num(plain, nan=-1.0), torch.nan_to_num(ordered, nan=-1.0))
+
+
+def test_track_order_entries_outside_are_skipped(torch, small_map):
+    w, counts, _, norm = small_map
+    mu, grid = R.source_map(counts, w.pix, norm, "disk", 2.0 * w.pix.Px)
+    tracks = W.light_curve_tracks(grid, 6, 1.0, seed=42)
+    dev = [torch.from_numpy(a).cuda() for a in tracks]
+    order = torch.tensor([5, -1, 0, 6, 1 << 30, 2], dtype=torch.int32, device="cuda")
+    for n_samples in (5, 100):
+        out = torch.full((6, n_samples), 1234.5, dtype=torch.float64, device="cuda")
+        R.light_curves(mu, grid, *dev, n_samples, out=out, order=order)
+        full = R.light_curves(mu, grid, *dev, n_samples)
+        for t in (0, 2, 5):
+            assert torch.equal(out[t], full[t])
+        for t in (1, 3, 4):
+            assert bool((out[t] == 1234.5).all())
