@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_INTERACTION = 10
 PROFILE = os.path.join(ROOT, "profiles", "shoot_fp64_kernel_plain-fp64-large.txt")
+PROFILE_LC = os.path.join(ROOT, "profiles", "light_curve_track_kernel_light-curves-large.txt")
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0              # MI355X HBM3E
 
@@ -48,6 +49,8 @@ def parse():
     ap.add_argument("--no-split", action="store_true", help="skip the many-stars/few-rays study")
     ap.add_argument("--no-expansion", action="store_true", help="skip the far-field expansion study")
     ap.add_argument("--no-light-curves", action="store_true", help="skip the light-curve timing")
+    ap.add_argument("--no-lc-given-order", action="store_true",
+                    help="time light curves in the track order only (not also in the given order)")
     ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
     ap.add_argument("--cpu-all-rays", type=int, default=2048,
                     help="side of the ray sample of the all-cores oracle run")
@@ -59,15 +62,15 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(workload_tag):
+def measured_traffic(workload_tag, profile=PROFILE, kernel="shoot_fp64_kernel"):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this kernel, or None when the kernel sources or the launch shape have
-    changed since the counters were taken."""
+    a kernel, or None when the kernel sources or the workload (launch shape)
+    have changed since the counters were taken."""
     from paper_1703_09707_amd import rocprof_summary as RS
-    s = RS.read_summary(PROFILE)
+    s = RS.read_summary(profile)
     if not s or "traffic_bytes_per_launch" not in s:
         return None
-    if s.get("source_sha256") != RS.source_hash("shoot_fp64_kernel") or s.get("workload") != workload_tag:
+    if s.get("source_sha256") != RS.source_hash(kernel) or s.get("workload") != workload_tag:
         return None
     return float(s["traffic_bytes_per_launch"])
 
@@ -205,7 +208,7 @@ def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup):
     return out
 
 
-def light_curve_section(torch, raysh, W, steps):
+def light_curve_section(torch, raysh, W, steps, given_order=True):
     """Light curves: the map of the large configuration seen by a Gaussian
     source of 2 pixels, then 2^20 straight tracks of 256 samples across it,
     visited in the library's track order (sorted once per track set).  The
@@ -235,13 +238,15 @@ def light_curve_section(torch, raysh, W, steps):
         c.record(stream)
         raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves, order=order)
         d.record(stream)
-        raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves)
+        if given_order:
+            raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves)
         e.record(stream)
         torch.cuda.synchronize()
         sm.append(a.elapsed_time(b))
         so.append(b.elapsed_time(c))
         lc.append(c.elapsed_time(d))
-        lu.append(d.elapsed_time(e))
+        if given_order:
+            lu.append(d.elapsed_time(e))
     lc_ms = sum(lc) / len(lc)
     samples = lw.n_tracks * lw.n_samples
     nbytes = samples * 8 + lw.n_tracks * (32 + 4) + mu.numel() * 8
@@ -250,11 +255,13 @@ def light_curve_section(torch, raysh, W, steps):
             "source_map_ms": sum(sm) / len(sm),
             "track_order_ms": sum(so) / len(so),
             "light_curve_kernel_ms": lc_ms,
-            "light_curve_kernel_ms_given_order": sum(lu) / len(lu),
+            "light_curve_kernel_ms_given_order": sum(lu) / len(lu) if lu else None,
             "samples_per_s": samples / (lc_ms * 1e-3),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "kernel": "light_curve_track_kernel",
-                         "bytes_per_launch": nbytes}}
+                         "bytes_per_launch": nbytes,
+                         "traffic": measured_traffic("light-curves-large 2^20 tracks x 256 samples, track order",
+                                                     PROFILE_LC, "light_curve_track_kernel")}}
 
 
 def cpu_baseline(w, side):
@@ -421,7 +428,7 @@ def main():
                                                   args.warmup)
     if not args.no_light_curves:
         print("# light curves", file=sys.stderr, flush=True)
-        out["light_curves"] = light_curve_section(torch, raysh, W, args.steps)
+        out["light_curves"] = light_curve_section(torch, raysh, W, args.steps, not args.no_lc_given_order)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)

@@ -27,6 +27,7 @@ KERNEL_SOURCES = {
     "finish_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "expansion_fp64_kernel": ["csrc/shoot_expansion.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "light_curve_kernel": ["csrc/light_curves.hip", "csrc/smooth.h"],
+    "light_curve_track_kernel": ["csrc/light_curves.hip", "csrc/smooth.h"],
 }
 
 
@@ -50,12 +51,16 @@ def kernel_stats(db):
     return _rows(db, "select name, total_calls, total_duration, average, percentage from top_kernels")
 
 
-def counter_values(db, name_like):
-    """{counter: [value per dispatch]} for kernels whose name contains name_like."""
+def counter_values(db, name_like, grid=None):
+    """{counter: [total per dispatch]} for kernels whose name contains
+    name_like, optionally only dispatches of one grid size (threads).  The
+    totals are rocprofv3's per-dispatch values, summed over the hardware
+    instances of each counter."""
     out = {}
-    for name, counter, value in _rows(db, "select name, counter_name, counter_value from pmc_events "
-                                          "where name like ?", (f"%{name_like}%",)):
-        out.setdefault(counter, []).append(value)
+    sql = "select counter_name, value, grid_size from counters_collection where kernel_name like ?"
+    for counter, value, g in _rows(db, sql, (f"%{name_like}%",)):
+        if grid is None or g == grid:
+            out.setdefault(counter, []).append(value)
     return out
 
 
@@ -70,11 +75,25 @@ def dispatch_durations_us(db, name_like, grid=None):
     return out
 
 
-def dispatch_waves(db, name_like):
+def per_instance_mean(db, name_like, counter, grid=None):
+    """Mean over hardware instances and dispatches of one counter (for
+    counters kept per XCD, such as GRBM_GUI_ACTIVE, whose instance mean is
+    the dispatch's length in cycles)."""
+    ids = {d for d, g in _rows(db, "select dispatch_id, grid_size from counters_collection "
+                                   "where kernel_name like ? and counter_name = ?", (f"%{name_like}%", counter))
+           if grid is None or g == grid}
+    vals = [v for d, v in _rows(db, "select dispatch_id, counter_value from pmc_events "
+                                    "where name like ? and counter_name = ?", (f"%{name_like}%", counter))
+            if d in ids]
+    return sum(vals) / len(vals) if vals else None
+
+
+def dispatch_waves(db, name_like, grid=None):
     """Waves of one dispatch of the kernel (grid size / 64)."""
-    rows = _rows(db, "select grid_size from counters_collection where kernel_name like ? limit 1",
-                 (f"%{name_like}%",))
-    return rows[0][0] / 64.0 if rows else None
+    for (g,) in _rows(db, "select grid_size from counters_collection where kernel_name like ?", (f"%{name_like}%",)):
+        if grid is None or g == grid:
+            return g / 64.0
+    return None
 
 
 def read_summary(path):
@@ -128,7 +147,7 @@ def main(argv=None):
         if not db:
             continue
         copy = counter_values(db, "copyBuffer").get(counter) or counter_values(db, "copy").get(counter)
-        kern = counter_values(db, a.kernel).get(counter)
+        kern = counter_values(db, a.kernel, a.grid).get(counter)
         if not copy or not kern:
             continue
         c = sum(copy) / len(copy)
@@ -143,17 +162,17 @@ def main(argv=None):
     if have == 2:
         lines.append(f"traffic_bytes_per_launch: {traffic:.0f}")
     if a.valu:
-        vals = counter_values(a.valu, a.kernel)
+        vals = counter_values(a.valu, a.kernel, a.grid)
         if vals:
             lines.append("")
             avg = {k: sum(v) / len(v) for k, v in vals.items()}
-            waves = dispatch_waves(a.valu, a.kernel)
-            # SQ counters are read from a subset of the shader engines; scale
-            # them by (waves of the dispatch) / (waves the counters saw)
+            waves = dispatch_waves(a.valu, a.kernel, a.grid)
+            # a check that the SQ counters saw every wave of the dispatch (1.0);
+            # were it below one, they would be scaled by it
             factor = waves / avg["SQ_WAVES"] if waves and avg.get("SQ_WAVES") else 1.0
             lines.append(f"dispatch_waves: {waves}")
             lines.append(f"sq_sample_factor: {factor:.3f}  (dispatch waves / SQ_WAVES)")
-            lines.append("VALU counters per dispatch (wave instructions, raw; then x sq_sample_factor):")
+            lines.append("VALU counters per dispatch (wave instructions; then x sq_sample_factor):")
             for k in sorted(avg):
                 scaled = avg[k] * factor if k.startswith("SQ_") else avg[k]
                 lines.append(f"  {k}: {avg[k]:.6e}  ->  {scaled:.6e}")
@@ -164,15 +183,16 @@ def main(argv=None):
             if k_avg:
                 sec = k_avg * 1e-6
                 lines.append(f"counter_tflops_fp64: {f64 / sec / 1e12:.3f}")
-                if "GRBM_GUI_ACTIVE" in avg:
-                    clock = avg["GRBM_GUI_ACTIVE"] / sec
-                    lines.append(f"mean_clock_ghz: {clock / 1e9:.3f}  (GRBM_GUI_ACTIVE / kernel time)")
+                grbm = per_instance_mean(a.valu, a.kernel, "GRBM_GUI_ACTIVE", a.grid)
+                if grbm:
+                    clock = grbm / sec
+                    lines.append(f"mean_clock_ghz: {clock / 1e9:.3f}  (GRBM_GUI_ACTIVE per XCD / kernel time)")
                 if "SQ_INSTS_VALU" in avg and waves:
                     simds = 1024   # 256 CUs x 4 SIMDs
                     busy = avg["SQ_INSTS_VALU"] * 4 / simds / sec
                     lines.append(f"valu_issue_cycles_per_second_per_simd: {busy:.4e}  "
                                  "(a wave64 VALU instruction takes 4 cycles of a 16-lane SIMD)")
-                    if "GRBM_GUI_ACTIVE" in avg:
+                    if grbm:
                         lines.append(f"valu_issue_fraction: {busy / clock:.3f}  (of the measured clock)")
             if a.flop_per_launch:
                 lines.append(f"algorithmic_flop_per_launch: {a.flop_per_launch:.6e}")
