@@ -12,9 +12,10 @@ network's predictions, with the realisation-noise floor (two star fields at
 the same parameters) and with a no-network baseline (the nearest training
 example in standardised feature space).
 
-Every numerical step runs in libraysh's kernels (raysh_map_batch,
-raysh_log_mag_histogram, raysh_mlp_*); this module marshals arguments,
-draws parameters and loops over batches.
+Every numerical step runs in libraysh's kernels (raysh_map_batch, or
+raysh_map per set for the expansion mode, raysh_log_mag_histogram,
+raysh_mlp_*); this module marshals arguments, draws parameters and loops
+over batches.
 """
 from __future__ import annotations
 
@@ -172,7 +173,9 @@ def generate(n_sets, seed, rays_per_side=4096, npix=512, window=10.0, sigmas_per
     """Shoot n_sets maps (lens parameters drawn as in workloads.draw_batch_params)
     and histogram each under sigmas_per_map Gaussian sources.  With `params`
     (a list of parameter dicts) the given sets are shot instead, with star
-    fields seeded by seed + star_seed_offset."""
+    fields seeded by seed + star_seed_offset.  The maps of a chunk are shot in
+    one batched launch ("fp64", "fp32_bulk") or one expansion-mode launch per
+    set ("fp64_expansion")."""
     torch = _torch()
     rng = np.random.Generator(np.random.PCG64(seed))
     if params is None:
@@ -196,7 +199,10 @@ def generate(n_sets, seed, rays_per_side=4096, npix=512, window=10.0, sigmas_per
             rays += rays_per_side ** 2
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        maps = R.map_batch(ctxs, grids, [pix] * len(part), precision)
+        if precision == "fp64_expansion":
+            maps = [c.map(g, pix, precision) for c, g in zip(ctxs, grids)]
+        else:
+            maps = R.map_batch(ctxs, grids, [pix] * len(part), precision)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         t_shoot += t1 - t0
@@ -310,7 +316,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--precision", default="fp32_bulk")
+    ap.add_argument("--precision", default="fp64_expansion",
+                    help="how the maps are shot: fp64_expansion, fp32_bulk or fp64")
     ap.add_argument("--seed", type=int, default=W.BASE_SEED + 4)
     ap.add_argument("--out", default=None, help="write the JSON result here too")
     a = ap.parse_args(argv)

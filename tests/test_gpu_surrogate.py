@@ -155,3 +155,16 @@ def test_network_beats_the_method_without_it(torch):
     assert res["l1_network"] < res["l1_nearest_neighbour"]
     assert per_example * 100 < shoot_per_map
     net.close()
+
+
+def test_generate_with_expansion_maps_matches_direct(torch):
+    """Training data shot with the far-field expansion is the data the
+    direct FP64 sum gives (the two bin the same rays up to the FP64 bar)."""
+    kw = dict(rays_per_side=1024, npix=256, sigmas_per_map=2, n_lo=300, n_hi=3000)
+    direct = S.generate(6, seed=31, precision="fp64", **kw)
+    fast = S.generate(6, seed=31, precision="fp64_expansion", **kw)
+    assert np.array_equal(direct.features, fast.features)
+    l1 = np.abs(direct.hist - fast.hist).sum(axis=1)
+    _say("expansion vs direct histograms: max L1", float(l1.max()),
+         f"shooting {direct.seconds_shooting:.3f} s direct, {fast.seconds_shooting:.3f} s expansion")
+    assert l1.max() < 1e-4
