@@ -283,29 +283,44 @@ __global__ __launch_bounds__(kThreads, 2) void expansion_fp64_kernel(ShootParams
 #pragma unroll
         for (int b = 0; b < kCY; ++b) ty[b] = image_angle(p.y0, p.j0 + tile_j + ly + kLanesY * b, p.dy);
         double ax[kCY][kCX], ay[kCY][kCX];
-#pragma unroll
-        for (int b = 0; b < kCY; ++b)
-#pragma unroll
-            for (int a = 0; a < kCX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
-
         if (!overflow) {
-            // far field: Horner in s = (z - c) / rho; f = alpha_x - i alpha_y
+            // far field: Horner in s = (z - c) / rho for the lane's rays
+            // together, one coefficient at a time (one LDS read each);
+            // f = alpha_x - i alpha_y is then added to the macro term
             const double inv_rho = 1.0 / rho;
+            double wx[kCX], wy[kCY];
 #pragma unroll
-            for (int b = 0; b < kCY; ++b) {
+            for (int a = 0; a < kCX; ++a) wx[a] = (tx[a] - cx) * inv_rho;
+#pragma unroll
+            for (int b = 0; b < kCY; ++b) wy[b] = (ty[b] - cy) * inv_rho;
+            const double2 top = ex.B[kOrder];
+#pragma unroll
+            for (int b = 0; b < kCY; ++b)
 #pragma unroll
                 for (int a = 0; a < kCX; ++a) {
-                    const double2 w = make_double2((tx[a] - cx) * inv_rho, (ty[b] - cy) * inv_rho);
-                    double2 F = ex.B[kOrder];
-                    for (int q = kOrder - 1; q >= 0; --q) {
-                        const double2 bq = ex.B[q];
-                        F = make_double2(__builtin_fma(F.x, w.x, __builtin_fma(-F.y, w.y, bq.x)),
-                                         __builtin_fma(F.x, w.y, __builtin_fma(F.y, w.x, bq.y)));
-                    }
-                    ax[b][a] += F.x;
-                    ay[b][a] -= F.y;
+                    ax[b][a] = top.x;
+                    ay[b][a] = top.y;
                 }
+            for (int q = kOrder - 1; q >= 0; --q) {
+                const double2 bq = ex.B[q];
+#pragma unroll
+                for (int b = 0; b < kCY; ++b)
+#pragma unroll
+                    for (int a = 0; a < kCX; ++a) {
+                        const double fx = ax[b][a], fy = ay[b][a];
+                        ax[b][a] = __builtin_fma(fx, wx[a], __builtin_fma(-fy, wy[b], bq.x));
+                        ay[b][a] = __builtin_fma(fx, wy[b], __builtin_fma(fy, wx[a], bq.y));
+                    }
             }
+#pragma unroll
+            for (int b = 0; b < kCY; ++b)
+#pragma unroll
+                for (int a = 0; a < kCX; ++a) {
+                    double mx, my;
+                    macro_term(p, tx[a], ty[b], mx, my);
+                    ax[b][a] = mx + ax[b][a];
+                    ay[b][a] = my - ay[b][a];
+                }
             // near stars, directly, in index order
             for (int w = 0; w < kWaves; ++w) {
                 const int cnt = uniform(near_n[w]);
@@ -313,6 +328,10 @@ __global__ __launch_bounds__(kThreads, 2) void expansion_fp64_kernel(ShootParams
             }
         } else {
             // too many near stars for the lists: every star directly
+#pragma unroll
+            for (int b = 0; b < kCY; ++b)
+#pragma unroll
+                for (int a = 0; a < kCX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
             for (int k = 0; k < n; ++k) direct_star(st, k, tx, ty, ax, ay);
         }
         finish_tile<kCX, kCY>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
