@@ -614,3 +614,28 @@ def test_star_upload_chunk_boundaries(torch, n_stars):
         assert np.all(np.abs(_np(gx) - ox) <= BETA_TOL * s)
         assert np.all(np.abs(_np(gy) - oy) <= BETA_TOL * s)
         assert np.count_nonzero(_np(gb) != ob) == 0
+
+
+@pytest.mark.parametrize("block", [1, 4])
+def test_expansion_degenerate_star_fields(torch, block):
+    """No stars, one star, massless stars, and a star exactly on a ray (that
+    ray is dropped, as in the oracle), in the expansion mode."""
+    rays = (-1.5, -1.25, 3 / 160, 2.5 / 130, 160, 130, 0, 0)
+    pix = (-2.0, -2.0, 4 / 64, 4 / 64, 64, 64)
+    tx0 = -1.5 + (37 + 0.5) * (3 / 160)   # the image angle of ray (37, 51)
+    ty0 = -1.25 + (51 + 0.5) * (2.5 / 130)
+    cases = [([], [], []), ([0.3], [-0.2], [1.0]), ([0.3, -0.4, 0.9], [-0.2, 0.5, 0.1], [0.0, 0.0, 0.0]),
+             ([tx0, 0.7], [ty0, -0.6], [0.5, 0.8])]
+    for xs, ys, ms in cases:
+        lens = (0.1, 0.2, -0.05, np.array(xs, float), np.array(ys, float), np.array(ms, float))
+        ox, oy, ob = ora.shoot(lens, rays, pix)
+        s = ora.error_scale_block(lens, rays)
+        with R.Context(lens) as ctx:
+            ctx.set_expansion_block(block)
+            gx, gy, gb = ctx.shoot(rays, "fp64_expansion", pix)
+            gx, gy, gb = _np(gx), _np(gy), _np(gb)
+            fin = np.isfinite(ox) & np.isfinite(oy)
+            assert np.array_equal(fin, np.isfinite(gx) & np.isfinite(gy)), (xs, block)
+            assert np.all(np.abs(gx[fin] - ox[fin]) <= BETA_TOL * s[fin])
+            assert np.all(np.abs(gy[fin] - oy[fin]) <= BETA_TOL * s[fin])
+            assert np.count_nonzero(gb != ob) == 0
