@@ -198,7 +198,9 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__global__ __launch_bounds__(kLcThreads) void light_curve_track_kernel(
+// Eight waves per SIMD (at most 64 VGPRs): the gathers' latency is hidden
+// by waves, not by work within one.
+__global__ __launch_bounds__(kLcThreads, 8) void light_curve_track_kernel(
     const double *__restrict__ mu, int nx, int ny, double x0, double y0, double ipx, double ipy,
     const double *__restrict__ xa, const double *__restrict__ ya, const double *__restrict__ xb,
     const double *__restrict__ yb, const int32_t *__restrict__ order, int64_t n_tracks, int64_t n_chunks,
