@@ -639,3 +639,45 @@ def test_expansion_degenerate_star_fields(torch, block):
             assert np.all(np.abs(gx[fin] - ox[fin]) <= BETA_TOL * s[fin])
             assert np.all(np.abs(gy[fin] - oy[fin]) <= BETA_TOL * s[fin])
             assert np.count_nonzero(gb != ob) == 0
+
+
+def _oracle_threaded(lens, rays, pix, threads):
+    """The oracle's per-ray results and error scale over a block of rays,
+    split into row bands on host threads (ctypes releases the GIL around
+    each call, and the oracle keeps no state between calls)."""
+    from concurrent.futures import ThreadPoolExecutor
+    ora.shoot(lens, rays.block(0, 0, 1, 1).as_tuple(), pix)   # loads the library once
+    edges = [rays.ny * k // threads for k in range(threads + 1)]
+
+    def run(k):
+        sub = rays.block(0, edges[k], rays.nx, edges[k + 1] - edges[k]).as_tuple()
+        bx, by, b = ora.shoot(lens, sub, pix)
+        return bx, by, b, ora.error_scale_block(lens, sub)
+
+    with ThreadPoolExecutor(threads) as pool:
+        parts = list(pool.map(run, range(threads)))
+    return [np.concatenate([p[i] for p in parts]) for i in range(4)]
+
+
+def test_large_config_full_band_every_ray(torch):
+    """A full-width band of the 8192^2 lattice of the large configuration
+    (rows 3840..4351, 4.2e6 rays x 16384 stars): every ray against the
+    oracle, for one-pass FP64, the expansion mode and FP32-bulk."""
+    w = W.plain_fp64_large()
+    band = w.rays.block(0, 3840, w.rays.nx, 512)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    _say(f"oracle on {band.nx}x{band.ny} rays, {threads} threads")
+    ox, oy, ob, s = _oracle_threaded(w.lens.as_tuple(), band, w.pix.as_tuple(), threads)
+    with R.Context(w.lens) as ctx:
+        for prec in ("fp64", "fp64_expansion"):
+            gx, gy, gb = (_np(t) for t in ctx.shoot(band, prec, w.pix))
+            mis = np.count_nonzero(gb != ob)
+            _say(prec, "misbinned", mis, "of", ob.size, "max |dbeta|/S",
+                 float(np.max(np.maximum(np.abs(gx - ox), np.abs(gy - oy)) / s)))
+            assert np.all(np.abs(gx - ox) <= BETA_TOL * s), prec
+            assert np.all(np.abs(gy - oy) <= BETA_TOL * s), prec
+            assert mis <= MISBIN_FP64 * ob.size, prec
+        _, _, fb = ctx.shoot(band, "fp32_bulk", w.pix, beta=False)
+        frac = np.count_nonzero(_np(fb) != ob) / ob.size
+        _say("fp32_bulk misbinned fraction against the oracle", frac)
+        assert frac <= MISBIN_FP32
