@@ -155,7 +155,8 @@ int raysh_set_expansion(raysh_ctx *ctx, double theta_open);
  * once, then re-tests only that block's near stars for each tile (block 1:
  * one tile, one test).  0 (the default) picks the block by a cost model:
  * a workgroup costs about n_stars + 16384 block^2 star-equivalents, and
- * workgroups run in rounds of two per compute unit.  The block
+ * workgroups run in rounds of three per compute unit (two from 65536
+ * stars on), a part-filled round counted in proportion.  The block
  * changes the order of floating-point operations, not the accuracy bound.
  * EINVAL for a NULL context or a block other than 0, 1, 2 or 4. */
 int raysh_set_expansion_block(raysh_ctx *ctx, int block);

@@ -32,6 +32,8 @@
 // With L = 1 the block is the tile and the second test is skipped.  If a
 // block has more near stars than its lists hold, its tiles sum every star
 // directly.
+#include <algorithm>
+
 #include "ray_common.h"
 
 namespace raysh {
@@ -43,6 +45,7 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kNearPerWave = 512;     // near-star list capacity of each wave
 constexpr int kCX = 4, kCY = 4;       // rays per lane
 constexpr int kTile = kLanesX * kCX;  // 64 rays per tile side
+constexpr int kManyStars = 65536;     // from here on, two workgroups per compute unit
 static_assert(kLanesX * kCX == kLanesY * kCY, "square tiles");
 
 struct ExpShared {
@@ -210,10 +213,13 @@ __device__ __forceinline__ void direct_star(const ConstStar *st, int k, const do
     }
 }
 
-// Two workgroups per compute unit: the compiler keeps to 256 VGPRs.
-template <int L>
-__global__ __launch_bounds__(kThreads, 2) void expansion_fp64_kernel(ShootParams p, double theta_open,
-                                                                  int blocks_x) {
+// WPS waves per SIMD (workgroups per compute unit): 3 suits few stars per
+// block, where the tiles' work dominates and more workgroups hide its
+// barriers; 2 suits many, where the pass over the stars dominates and
+// needs its registers (at 3 it spills a few values inside that loop).
+template <int L, int WPS>
+__global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootParams p, double theta_open,
+                                                                       int blocks_x) {
     __shared__ BinShared sh;
     __shared__ ExpShared ex;
     bin_shared_init(sh);
@@ -344,8 +350,12 @@ template <int L>
 hipError_t launch_level(const ShootParams &p, double theta_open, int64_t tiles_x, int64_t tiles_y,
                         hipStream_t s) {
     const int64_t bx = (tiles_x + L - 1) / L, by = (tiles_y + L - 1) / L;
-    hipLaunchKernelGGL((expansion_fp64_kernel<L>), dim3((unsigned)(bx * by)), dim3(kThreads), 0, s, p, theta_open,
-                       (int)bx);
+    if (p.n_stars < kManyStars)
+        hipLaunchKernelGGL((expansion_fp64_kernel<L, 3>), dim3((unsigned)(bx * by)), dim3(kThreads), 0, s, p,
+                           theta_open, (int)bx);
+    else
+        hipLaunchKernelGGL((expansion_fp64_kernel<L, 2>), dim3((unsigned)(bx * by)), dim3(kThreads), 0, s, p,
+                           theta_open, (int)bx);
     return hipGetLastError();
 }
 
@@ -356,16 +366,17 @@ int expansion_order() { return kOrder; }
 // The block that minimises a simple cost model: a workgroup costs about
 // N* + 16384 L^2 star-equivalents (its pass over all stars, then L^2 tiles
 // of Horner steps, near stars and binning, measured on MI355X), and the
-// workgroups run in rounds of two per compute unit.
+// workgroups run in rounds of three (two from kManyStars stars on) per
+// compute unit, a part-filled round counted in proportion.
 int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu) {
     const int64_t tx = (nx + kTile - 1) / kTile, ty = (ny + kTile - 1) / kTile;
-    const int64_t slots = 2 * (int64_t)(n_cu > 0 ? n_cu : 256);
+    const int64_t slots = (n_stars < kManyStars ? 3 : 2) * (int64_t)(n_cu > 0 ? n_cu : 256);
     int best = 1;
     double best_cost = 0.0;
     for (int L : {1, 2, 4}) {
         const int64_t blocks = ((tx + L - 1) / L) * ((ty + L - 1) / L);
-        const int64_t rounds = (blocks + slots - 1) / slots;
-        const double cost = (double)rounds * ((double)n_stars + 16384.0 * L * L);
+        const double rounds = std::max(1.0, (double)blocks / (double)slots);   // a part-filled round runs faster
+        const double cost = rounds * ((double)n_stars + 16384.0 * L * L);
         if (L == 1 || cost < best_cost) {
             best = L;
             best_cost = cost;
