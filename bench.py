@@ -171,7 +171,7 @@ def split_section(torch, raysh, W):
 
 
 def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup):
-    """FP64 with the far field of each ray tile as a local expansion, on the
+    """FP64 with the far field of the star sum as local expansions, on the
     large configuration (time per map against the one-pass FP64 map, and the
     fraction of rays binned differently), and on the central 2048^2 rays of
     the 262144-star precision-study lattice."""
