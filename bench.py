@@ -211,7 +211,8 @@ def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup):
 def light_curve_section(torch, raysh, W, steps, given_order=True):
     """Light curves: the map of the large configuration seen by a Gaussian
     source of 2 pixels, then 2^20 straight tracks of 256 samples across it,
-    visited in the library's track order (sorted once per track set).  The
+    visited in the library's track order, with the end points in that order
+    (both computed once per track set).  The
     light-curve kernel is a gather bound by HBM: its algorithmic bytes are
     the curves written, the track end points read and the source map read
     once."""
@@ -225,8 +226,8 @@ def light_curve_section(torch, raysh, W, steps, given_order=True):
     mu, grid = raysh.source_map(counts, w.pix, norm, lw.profile, lw.size)
     tracks = [torch.from_numpy(a).cuda() for a in W.light_curve_tracks(grid, lw.n_tracks, lw.length)]
     curves = torch.empty((lw.n_tracks, lw.n_samples), dtype=torch.float64, device="cuda")
-    order = raysh.track_order(grid, *tracks)
-    raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves, order=order)
+    order, srt = raysh.track_order(grid, *tracks, sorted_end_points=True)
+    raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves, order=order, sorted=srt)
     torch.cuda.synchronize()
     sm, so, lc, lu = [], [], [], []
     for _ in range(steps):
@@ -234,9 +235,9 @@ def light_curve_section(torch, raysh, W, steps, given_order=True):
         a.record(stream)
         mu, grid = raysh.source_map(counts, w.pix, norm, lw.profile, lw.size)
         b.record(stream)
-        order = raysh.track_order(grid, *tracks)
+        order, srt = raysh.track_order(grid, *tracks, sorted_end_points=True)
         c.record(stream)
-        raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves, order=order)
+        raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves, order=order, sorted=srt)
         d.record(stream)
         if given_order:
             raysh.light_curves(mu, grid, *tracks, lw.n_samples, out=curves)
@@ -249,7 +250,7 @@ def light_curve_section(torch, raysh, W, steps, given_order=True):
             lu.append(d.elapsed_time(e))
     lc_ms = sum(lc) / len(lc)
     samples = lw.n_tracks * lw.n_samples
-    nbytes = samples * 8 + lw.n_tracks * (32 + 4) + mu.numel() * 8
+    nbytes = samples * 8 + lw.n_tracks * (32 + 4) + mu.numel() * 8   # curves, end points + order, map
     achieved = nbytes / (lc_ms * 1e-3) / 1e9
     return {"workload": lw.name, "samples": samples,
             "source_map_ms": sum(sm) / len(sm),

@@ -355,15 +355,19 @@ int raysh_source_map(const int32_t *counts, int32_t nx, int32_t ny, double norm,
  *   order: NULL (tracks in the order given) or device int32[n_tracks], a
  *          permutation of the tracks in which to visit them (as written by
  *          raysh_track_order).  The curves are the same either way: row t
- *          of curves is track t.  Entries outside [0, n_tracks) are skipped.
+ *          of curves is track t.  Entries outside [0, n_tracks) are skipped;
+ *   sorted: NULL, or (with order) device FP64[4][n_tracks]: the end points
+ *          xa, ya, xb, yb in visiting order (as written by
+ *          raysh_track_order), read in place of xa[order[i]] etc.; faster
+ *          because they are read beside the order instead of after it.
  * Asynchronous on hip_stream, on mu_s's device.  n_tracks == 0 is a no-op.
  * EINVAL on a bad grid, n_tracks < 0, n_samples outside [1, 2^24], NULL or
- * non-device buffers; EOVERFLOW above 2^31-1 map pixels or (2^31-1) * 256
- * samples.
+ * non-device buffers, or sorted without order; EOVERFLOW above 2^31-1 map
+ * pixels or (2^31-1) * 1024 samples.
  */
 int raysh_light_curves(const double *mu_s, const raysh_pixels *grid, int64_t n_tracks, int32_t n_samples,
                        const double *xa, const double *ya, const double *xb, const double *yb,
-                       const int32_t *order, double *curves, void *hip_stream);
+                       const int32_t *order, const double *sorted, double *curves, void *hip_stream);
 
 /* Device workspace, in bytes, that raysh_track_order needs for a source map
  * of pixel grid `grid` (0 for an invalid grid). */
@@ -380,6 +384,9 @@ size_t raysh_track_order_workspace(const raysh_pixels *grid);
  *                   raysh_light_curves);
  *   order:          device int32[n_tracks], overwritten with a permutation
  *                   of 0 .. n_tracks - 1;
+ *   sorted:         NULL, or device FP64[4][n_tracks], overwritten with the
+ *                   end points in that order (xa[order[i]] at [0][i],
+ *                   ya at [1][i], xb at [2][i], yb at [3][i]);
  *   workspace:      device memory of raysh_track_order_workspace(grid) bytes.
  * Asynchronous on hip_stream, on xa's device.  n_tracks == 0 is a no-op.
  * EINVAL on a bad grid, n_tracks < 0, NULL or non-device buffers or a short
@@ -387,7 +394,7 @@ size_t raysh_track_order_workspace(const raysh_pixels *grid);
  */
 int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, const double *xa, const double *ya,
                       const double *xb, const double *yb, void *workspace, size_t workspace_bytes, int32_t *order,
-                      void *hip_stream);
+                      double *sorted, void *hip_stream);
 
 /*
  * The network: layers n_in -> n_hidden -> n_hidden -> n_out, GELU (erf

@@ -110,14 +110,14 @@ constexpr int kSpt = 4;
 __global__ __launch_bounds__(kLcThreads) void light_curve_kernel(
     const double *__restrict__ mu, int nx, int ny, double x0, double y0, double ipx, double ipy,
     const double *__restrict__ xa, const double *__restrict__ ya, const double *__restrict__ xb,
-    const double *__restrict__ yb, const int32_t *__restrict__ order, int64_t n_tracks, int n_samples,
-    float inv_nf, double inv_n1, double *__restrict__ out) {
+    const double *__restrict__ yb, const int32_t *__restrict__ order, const double *__restrict__ sorted,
+    int64_t n_tracks, int n_samples, float inv_nf, double inv_n1, double *__restrict__ out) {
 #pragma clang fp contract(off)
     const int64_t base = (int64_t)blockIdx.x * (kSpt * kLcThreads);
     const int64_t total = n_tracks * (int64_t)n_samples;
     const int64_t t0 = base / n_samples;
     const int r0 = (int)(base - t0 * n_samples) + (int)threadIdx.x;
-    int64_t t[kSpt];
+    int64_t t[kSpt], tv[kSpt];   // track (row of out), and its visit index
     int k[kSpt];
     bool live[kSpt];
 #pragma unroll
@@ -134,6 +134,7 @@ __global__ __launch_bounds__(kLcThreads) void light_curve_kernel(
         }
         live[e] = base + threadIdx.x + e * kLcThreads < total;
         int64_t tt = t0 + q;
+        tv[e] = live[e] ? tt : 0;
         if (order && live[e]) {
             tt = order[tt];
             live[e] = tt >= 0 && tt < n_tracks;   // entries outside the tracks are skipped
@@ -144,10 +145,17 @@ __global__ __launch_bounds__(kLcThreads) void light_curve_kernel(
     double ax[kSpt], ay[kSpt], bx[kSpt], by[kSpt];
 #pragma unroll
     for (int e = 0; e < kSpt; ++e) {
-        ax[e] = xa[t[e]];
-        ay[e] = ya[t[e]];
-        bx[e] = xb[t[e]];
-        by[e] = yb[t[e]];
+        if (sorted) {
+            ax[e] = sorted[tv[e]];
+            ay[e] = sorted[n_tracks + tv[e]];
+            bx[e] = sorted[2 * n_tracks + tv[e]];
+            by[e] = sorted[3 * n_tracks + tv[e]];
+        } else {
+            ax[e] = xa[t[e]];
+            ay[e] = ya[t[e]];
+            bx[e] = xb[t[e]];
+            by[e] = yb[t[e]];
+        }
     }
     double fx[kSpt], fy[kSpt], m00[kSpt], m01[kSpt], m10[kSpt], m11[kSpt];
     bool inside[kSpt];
@@ -203,26 +211,40 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
 __global__ __launch_bounds__(kLcThreads, 8) void light_curve_track_kernel(
     const double *__restrict__ mu, int nx, int ny, double x0, double y0, double ipx, double ipy,
     const double *__restrict__ xa, const double *__restrict__ ya, const double *__restrict__ xb,
-    const double *__restrict__ yb, const int32_t *__restrict__ order, int64_t n_tracks, int64_t n_chunks,
-    int chunks_per_track, int n_samples, double inv_n1, double *__restrict__ out) {
+    const double *__restrict__ yb, const int32_t *__restrict__ order, const double *__restrict__ sorted,
+    int64_t n_tracks, int64_t n_chunks, int chunks_per_track, int n_samples, double inv_n1,
+    double *__restrict__ out) {
 #pragma clang fp contract(off)
     const int64_t chunk = wave_uniform((int64_t)blockIdx.x * (kLcThreads / 64) + threadIdx.x / 64);
     if (chunk >= n_chunks) return;   // uniform in the wave
     const int64_t tp = chunk / chunks_per_track;
     const int k0 = (int)(chunk - tp * chunks_per_track) * kWaveChunk;
     int64_t t = tp;
+    double ax, ay, bx, by;
     if (order) {
         t = ((const __attribute__((address_space(4))) int32_t *)order)[tp];
+        if (sorted) {   // end points in visiting order: read beside the order, not after it
+            const ConstDouble *cs = (const ConstDouble *)sorted;
+            ax = cs[tp];
+            ay = cs[n_tracks + tp];
+            bx = cs[2 * n_tracks + tp];
+            by = cs[3 * n_tracks + tp];
+        }
         if (t < 0 || t >= n_tracks) return;   // uniform: entries outside the tracks are skipped
     }
+    if (!sorted) {
+        const ConstDouble *cxa = (const ConstDouble *)xa, *cya = (const ConstDouble *)ya;
+        const ConstDouble *cxb = (const ConstDouble *)xb, *cyb = (const ConstDouble *)yb;
+        ax = cxa[t];
+        ay = cya[t];
+        bx = cxb[t];
+        by = cyb[t];
+    }
     const int lane = threadIdx.x % 64;
-    const ConstDouble *cxa = (const ConstDouble *)xa, *cya = (const ConstDouble *)ya;
-    const ConstDouble *cxb = (const ConstDouble *)xb, *cyb = (const ConstDouble *)yb;
-    const double ax = cxa[t], ay = cya[t];
     const double ua = (ax - x0) * ipx - 0.5;
     const double va = (ay - y0) * ipy - 0.5;
-    const double du = ((cxb[t] - ax) * ipx) * inv_n1;
-    const double dv = ((cyb[t] - ay) * ipy) * inv_n1;
+    const double du = ((bx - ax) * ipx) * inv_n1;
+    const double dv = ((by - ay) * ipy) * inv_n1;
     double fx[kSpt], fy[kSpt], m00[kSpt], m01[kSpt], m10[kSpt], m11[kSpt];
     bool inside[kSpt];
 #pragma unroll
@@ -352,11 +374,18 @@ __global__ __launch_bounds__(kScanThreads) void track_scan_kernel(uint32_t *coun
 __global__ __launch_bounds__(kLcThreads) void track_scatter_kernel(CellGrid c, const double *xa, const double *ya,
                                                                    const double *xb, const double *yb,
                                                                    int64_t n_tracks, uint32_t *offsets,
-                                                                   int32_t *order) {
+                                                                   int32_t *order, double *sorted) {
     const int64_t t = (int64_t)blockIdx.x * kLcThreads + threadIdx.x;
     if (t >= n_tracks) return;
-    const uint32_t pos = atomicAdd(&offsets[track_key(c, xa[t], ya[t], xb[t], yb[t])], 1u);
+    const double ax = xa[t], ay = ya[t], bx = xb[t], by = yb[t];
+    const uint32_t pos = atomicAdd(&offsets[track_key(c, ax, ay, bx, by)], 1u);
     order[pos] = (int32_t)t;   // pos < n_tracks: the offsets partition [0, n_tracks)
+    if (sorted) {
+        sorted[pos] = ax;
+        sorted[n_tracks + pos] = ay;
+        sorted[2 * n_tracks + pos] = bx;
+        sorted[3 * n_tracks + pos] = by;
+    }
 }
 
 int check_profile(int profile, double size, double px, double py, int32_t nx, int32_t ny) {
@@ -461,7 +490,7 @@ extern "C" size_t raysh_track_order_workspace(const raysh_pixels *grid) {
 
 extern "C" int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, const double *xa, const double *ya,
                                  const double *xb, const double *yb, void *workspace, size_t workspace_bytes,
-                                 int32_t *order, void *hip_stream) {
+                                 int32_t *order, double *sorted, void *hip_stream) {
     if (!grid) return set_error(RAYSH_EINVAL, "raysh_track_order: grid is NULL");
     if (int r = validate_pixels(grid)) return r;
     if (n_tracks < 0) return set_error(RAYSH_EINVAL, "n_tracks < 0");
@@ -486,6 +515,8 @@ extern "C" int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, con
     if (int r = validate_device_ptr(xb, tb, device, "xb")) return r;
     if (int r = validate_device_ptr(yb, tb, device, "yb")) return r;
     if (int r = validate_device_ptr(order, (size_t)n_tracks * 4, device, "order")) return r;
+    if (sorted)
+        if (int r = validate_device_ptr(sorted, (size_t)n_tracks * 32, device, "sorted")) return r;
     if (int r = validate_device_ptr(workspace, need, device, "workspace")) return r;
 
     hipStream_t s = (hipStream_t)hip_stream;
@@ -498,7 +529,7 @@ extern "C" int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, con
                        counts);
     hipLaunchKernelGGL(track_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, n_keys);
     hipLaunchKernelGGL(track_scatter_kernel, dim3(tb_blocks), dim3(kLcThreads), 0, s, c, xa, ya, xb, yb, n_tracks,
-                       counts, order);
+                       counts, order, sorted);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "raysh_track_order");
     return set_ok();
@@ -506,7 +537,8 @@ extern "C" int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, con
 
 extern "C" int raysh_light_curves(const double *mu_s, const raysh_pixels *grid, int64_t n_tracks,
                                   int32_t n_samples, const double *xa, const double *ya, const double *xb,
-                                  const double *yb, const int32_t *order, double *curves, void *hip_stream) {
+                                  const double *yb, const int32_t *order, const double *sorted, double *curves,
+                                  void *hip_stream) {
     if (!grid) return set_error(RAYSH_EINVAL, "raysh_light_curves: grid is NULL");
     if (int r = validate_pixels(grid)) return r;
     if (grid->nx < 2 || grid->ny < 2) return set_error(RAYSH_EINVAL, "the source map needs at least 2 x 2 pixels");
@@ -538,6 +570,9 @@ extern "C" int raysh_light_curves(const double *mu_s, const raysh_pixels *grid, 
     if (int r = validate_device_ptr(curves, (size_t)total * 8, device, "curves")) return r;
     if (order)
         if (int r = validate_device_ptr(order, (size_t)n_tracks * 4, device, "order")) return r;
+    if (sorted && !order) return set_error(RAYSH_EINVAL, "sorted end points need their order");
+    if (sorted)
+        if (int r = validate_device_ptr(sorted, (size_t)n_tracks * 32, device, "sorted")) return r;
 
     hipStream_t s = (hipStream_t)hip_stream;
     const double inv_n1 = n_samples > 1 ? 1.0 / (double)(n_samples - 1) : 0.0;
@@ -551,13 +586,13 @@ extern "C" int raysh_light_curves(const double *mu_s, const raysh_pixels *grid, 
         hipLaunchKernelGGL(light_curve_track_kernel,
                            dim3((unsigned)((n_chunks + waves_per_block - 1) / waves_per_block)), dim3(kLcThreads), 0,
                            s, mu_s, grid->nx, grid->ny, grid->x0, grid->y0, 1.0 / grid->px, 1.0 / grid->py, xa, ya, xb,
-                           yb, order, n_tracks, n_chunks, chunks_per_track, n_samples, inv_n1, curves);
+                           yb, order, sorted, n_tracks, n_chunks, chunks_per_track, n_samples, inv_n1, curves);
     } else {
         const float inv_nf = 1.0f / (float)n_samples;                   // n_samples <= 2^24: exact in float
         hipLaunchKernelGGL(light_curve_kernel,
                            dim3((unsigned)((total + kSpt * kLcThreads - 1) / (kSpt * kLcThreads))), dim3(kLcThreads),
                            0, s, mu_s, grid->nx, grid->ny, grid->x0, grid->y0, 1.0 / grid->px, 1.0 / grid->py, xa, ya,
-                           xb, yb, order, n_tracks, n_samples, inv_nf, inv_n1, curves);
+                           xb, yb, order, sorted, n_tracks, n_samples, inv_nf, inv_n1, curves);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "raysh_light_curves");

@@ -117,11 +117,12 @@ def load():
     lib.raysh_source_map.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, I, D, D, D, P, ctypes.c_size_t, P, P]
     lib.raysh_source_map.restype = I
     lib.raysh_light_curves.argtypes = [P, ctypes.POINTER(Pixels), ctypes.c_int64, ctypes.c_int32,
-                                       P, P, P, P, P, P, P]
+                                       P, P, P, P, P, P, P, P]
     lib.raysh_light_curves.restype = I
     lib.raysh_track_order_workspace.argtypes = [ctypes.POINTER(Pixels)]
     lib.raysh_track_order_workspace.restype = ctypes.c_size_t
-    lib.raysh_track_order.argtypes = [ctypes.POINTER(Pixels), ctypes.c_int64, P, P, P, P, P, ctypes.c_size_t, P, P]
+    lib.raysh_track_order.argtypes = [ctypes.POINTER(Pixels), ctypes.c_int64, P, P, P, P, P, ctypes.c_size_t, P, P,
+                                      P]
     lib.raysh_track_order.restype = I
     F = ctypes.c_float
     lib.raysh_mlp_create.argtypes = [ctypes.POINTER(P), I, P, ctypes.c_int32, ctypes.c_int32,
@@ -367,9 +368,11 @@ def source_map(counts, pix, norm, profile="gaussian", size=0.05, stream=None):
     return out, grid
 
 
-def track_order(grid, xa, ya, xb, yb, stream=None):
+def track_order(grid, xa, ya, xb, yb, sorted_end_points=False, stream=None):
     """raysh_track_order: a visiting order (int32 device permutation) of the
-    tracks in which neighbouring tracks read neighbouring parts of the map."""
+    tracks in which neighbouring tracks read neighbouring parts of the map.
+    With sorted_end_points, also the end points in that order (FP64
+    [4, n_tracks]); returns (order, sorted) then."""
     torch = _torch()
     g = pixels_struct(grid)
     n = int(xa.numel())
@@ -378,16 +381,18 @@ def track_order(grid, xa, ya, xb, yb, stream=None):
     lib = load()
     ws = torch.empty(max(1, lib.raysh_track_order_workspace(ctypes.byref(g))), dtype=torch.uint8, device=xa.device)
     order = torch.empty(n, dtype=torch.int32, device=xa.device)
+    srt = torch.empty((4, n), dtype=torch.float64, device=xa.device) if sorted_end_points else None
     check(lib.raysh_track_order(ctypes.byref(g), n, _ptr(xa), _ptr(ya), _ptr(xb), _ptr(yb), _ptr(ws), ws.numel(),
-                                _ptr(order), _stream_handle(torch, xa.device, stream)))
-    return order
+                                _ptr(order), _ptr(srt), _stream_handle(torch, xa.device, stream)))
+    return (order, srt) if sorted_end_points else order
 
 
-def light_curves(mu_s, grid, xa, ya, xb, yb, n_samples, out=None, order=None, stream=None):
+def light_curves(mu_s, grid, xa, ya, xb, yb, n_samples, out=None, order=None, sorted=None, stream=None):
     """raysh_light_curves: tracks (xa, ya) -> (xb, yb) (FP64 device arrays)
     sampled at n_samples points across the source map mu_s of pixel grid
-    `grid`, visited in `order` when given (see track_order).  Returns FP64
-    (n_tracks, n_samples), NaN outside the map; row t is track t."""
+    `grid`, visited in `order` when given, with the end points read from
+    `sorted` when given (see track_order).  Returns FP64 (n_tracks,
+    n_samples), NaN outside the map; row t is track t."""
     torch = _torch()
     g = pixels_struct(grid)
     n = int(xa.numel())
@@ -396,10 +401,12 @@ def light_curves(mu_s, grid, xa, ya, xb, yb, n_samples, out=None, order=None, st
     assert tuple(mu_s.shape) == (g.ny, g.nx) and all(int(a.numel()) == n for a in (ya, xb, yb))
     if order is not None:
         assert order.dtype == torch.int32 and order.is_contiguous() and int(order.numel()) == n
+    if sorted is not None:
+        assert sorted.dtype == torch.float64 and sorted.is_contiguous() and tuple(sorted.shape) == (4, n)
     if out is None:
         out = torch.empty((n, int(n_samples)), dtype=torch.float64, device=mu_s.device)
     assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == n * int(n_samples)
     check(load().raysh_light_curves(_ptr(mu_s), ctypes.byref(g), n, int(n_samples), _ptr(xa), _ptr(ya),
-                                    _ptr(xb), _ptr(yb), _ptr(order), _ptr(out),
+                                    _ptr(xb), _ptr(yb), _ptr(order), _ptr(sorted), _ptr(out),
                                     _stream_handle(torch, mu_s.device, stream)))
     return out

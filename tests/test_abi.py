@@ -234,14 +234,14 @@ def test_source_map_and_light_curve_argument_errors(lib):
     lc = lib.raysh_light_curves
     g = R.Pixels(0.0, 0.0, 0.1, 0.1, 16, 16)
     d = dummy
-    assert lc(d, None, 4, 8, d, d, d, d, None, d, None) == R.EINVAL
-    assert lc(d, ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 1, 16)), 4, 8, d, d, d, d, None, d, None) == R.EINVAL
-    assert lc(d, ctypes.byref(g), -1, 8, d, d, d, d, None, d, None) == R.EINVAL
-    assert lc(d, ctypes.byref(g), 4, 0, d, d, d, d, None, d, None) == R.EINVAL
-    assert lc(d, ctypes.byref(g), 4, (1 << 24) + 1, d, d, d, d, None, d, None) == R.EINVAL
-    assert lc(d, ctypes.byref(g), 1 << 40, 1 << 20, d, d, d, d, None, d, None) == R.EOVERFLOW
-    assert lc(d, ctypes.byref(g), 4, 8, None, d, d, d, None, d, None) == R.EINVAL
-    assert lc(None, ctypes.byref(g), 0, 8, None, None, None, None, None, None, None) == R.OK   # no tracks: no-op
+    assert lc(d, None, 4, 8, d, d, d, d, None, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 1, 16)), 4, 8, d, d, d, d, None, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(g), -1, 8, d, d, d, d, None, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(g), 4, 0, d, d, d, d, None, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(g), 4, (1 << 24) + 1, d, d, d, d, None, None, d, None) == R.EINVAL
+    assert lc(d, ctypes.byref(g), 1 << 40, 1 << 20, d, d, d, d, None, None, d, None) == R.EOVERFLOW
+    assert lc(d, ctypes.byref(g), 4, 8, None, d, d, d, None, None, d, None) == R.EINVAL
+    assert lc(None, ctypes.byref(g), 0, 8, None, None, None, None, None, None, None, None) == R.OK   # no tracks: no-op
     to = lib.raysh_track_order
     assert lib.raysh_track_order_workspace(None) == 0
     assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 0, 16))) == 0
@@ -250,10 +250,10 @@ def test_source_map_and_light_curve_argument_errors(lib):
     # 40000 pixels a side: cells grow to 32 pixels (1250 a side), keys over 2048 x 2048
     assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 40000, 100))) == \
         4 * (2048 * 2048 + 1)
-    assert to(None, 4, d, d, d, d, d, 1 << 30, d, None) == R.EINVAL
-    assert to(ctypes.byref(g), -1, d, d, d, d, d, 1 << 30, d, None) == R.EINVAL
-    assert to(ctypes.byref(g), 1 << 31, d, d, d, d, d, 1 << 30, d, None) == R.EOVERFLOW
-    assert to(ctypes.byref(g), 4, d, d, d, d, d, 4, d, None) == R.EINVAL
+    assert to(None, 4, d, d, d, d, d, 1 << 30, d, None, None) == R.EINVAL
+    assert to(ctypes.byref(g), -1, d, d, d, d, d, 1 << 30, d, None, None) == R.EINVAL
+    assert to(ctypes.byref(g), 1 << 31, d, d, d, d, d, 1 << 30, d, None, None) == R.EOVERFLOW
+    assert to(ctypes.byref(g), 4, d, d, d, d, d, 4, d, None, None) == R.EINVAL
     assert "workspace" in _err(lib)
-    assert to(ctypes.byref(g), 4, d, None, d, d, d, 1 << 30, d, None) == R.EINVAL
-    assert to(ctypes.byref(g), 0, None, None, None, None, None, 0, None, None) == R.OK
+    assert to(ctypes.byref(g), 4, d, None, d, d, d, 1 << 30, d, None, None) == R.EINVAL
+    assert to(ctypes.byref(g), 0, None, None, None, None, None, 0, None, None, None) == R.OK

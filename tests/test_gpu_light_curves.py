@@ -94,8 +94,8 @@ def test_light_curves_large_workload(torch):
     tracks = W.light_curve_tracks(grid, lw.n_tracks, lw.length)
     dev = [torch.from_numpy(a).cuda() for a in tracks]
     _say("light curves (large)")
-    order = R.track_order(grid, *dev)
-    curves = R.light_curves(mu, grid, *dev, lw.n_samples, order=order)
+    order, srt = R.track_order(grid, *dev, sorted_end_points=True)
+    curves = R.light_curves(mu, grid, *dev, lw.n_samples, order=order, sorted=srt)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(curves).all())
     rng = np.random.default_rng(5)
@@ -119,20 +119,24 @@ def test_source_map_and_light_curve_errors(torch, small_map):
     import ctypes
     code = lib.raysh_light_curves(ctypes.c_void_p(mu.data_ptr()), ctypes.byref(g), 4, 8,
                                   host.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(mu.data_ptr()),
-                                  ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(mu.data_ptr()), None,
+                                  ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(mu.data_ptr()), None, None,
                                   ctypes.c_void_p(mu.data_ptr()), None)
     assert code == R.EINVAL and "xa" in lib.raysh_last_error().decode()
     tiny = torch.zeros(3, dtype=torch.float64, device="cuda")
     t = ctypes.c_void_p(tiny.data_ptr())
     code = lib.raysh_light_curves(ctypes.c_void_p(mu.data_ptr()), ctypes.byref(g), 1 << 26, 8, t, t, t, t, None,
-                                  ctypes.c_void_p(mu.data_ptr()), None)     # 512 MiB per track array
+                                  None, ctypes.c_void_p(mu.data_ptr()), None)     # 512 MiB per track array
     assert code == R.EINVAL and "needed" in lib.raysh_last_error().decode()
     assert int(tiny.abs().sum()) == 0
     n4 = torch.zeros(4, dtype=torch.float64, device="cuda")
     p4 = ctypes.c_void_p(n4.data_ptr())
     code = lib.raysh_light_curves(ctypes.c_void_p(mu.data_ptr()), ctypes.byref(g), 4, 8, p4, p4, p4, p4,
-                                  host.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(mu.data_ptr()), None)
+                                  host.ctypes.data_as(ctypes.c_void_p), None, ctypes.c_void_p(mu.data_ptr()), None)
     assert code == R.EINVAL and "order" in lib.raysh_last_error().decode()
+    s16 = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
+    code = lib.raysh_light_curves(ctypes.c_void_p(mu.data_ptr()), ctypes.byref(g), 4, 8, p4, p4, p4, p4, None,
+                                  ctypes.c_void_p(s16.data_ptr()), ctypes.c_void_p(mu.data_ptr()), None)
+    assert code == R.EINVAL and "sorted" in lib.raysh_last_error().decode()
 
 
 def test_track_order(torch, small_map):
@@ -151,11 +155,16 @@ def test_track_order(torch, small_map):
     step = lambda idx: np.hypot(np.diff(mx[idx]), np.diff(my[idx])).mean()   # noqa: E731
     _say("mean step between consecutive midpoints: given", step(np.arange(len(o))), "ordered", step(o))
     assert step(o) < 0.1 * step(np.arange(len(o)))
+    order2, srt = R.track_order(grid, *dev, sorted_end_points=True)
+    o2 = order2.cpu().numpy()
+    assert np.array_equal(np.sort(o2), np.arange(len(o2)))
+    assert np.array_equal(srt.cpu().numpy(), np.stack([a[o2] for a in tracks]))
     for n_samples in (7, 300):
         plain = R.light_curves(mu, grid, *dev, n_samples)
-        ordered = R.light_curves(mu, grid, *dev, n_samples, order=order)
-        assert torch.equal(torch.isnan(plain), torch.isnan(ordered))
-        assert torch.equal(torch.nan_to_num(plain, nan=-1.0), torch.nan_to_num(ordered, nan=-1.0))
+        for kw in (dict(order=order), dict(order=order2, sorted=srt)):
+            ordered = R.light_curves(mu, grid, *dev, n_samples, **kw)
+            assert torch.equal(torch.isnan(plain), torch.isnan(ordered))
+            assert torch.equal(torch.nan_to_num(plain, nan=-1.0), torch.nan_to_num(ordered, nan=-1.0))
 
 
 def test_track_order_entries_outside_are_skipped(torch, small_map):
