@@ -21,10 +21,9 @@
 // Two levels.  A workgroup owns a block of L x L ray tiles (a tile is
 // 64 x 64 rays, 4 x 4 per lane as in the one-pass kernel).  It expands the
 // stars far from the whole block once (every star is visited once per
-// block, not once per tile), keeping the block's near stars in lists.  For
-// each tile it then
-//   * re-centres the block's polynomial on the tile (the shift of a
-//     polynomial is exact algebra: no new truncation),
+// block, not once per tile), keeping the block's near stars in lists, and
+// re-centres the block's polynomial on every tile at once (the shift of a
+// polynomial is exact algebra: no new truncation).  For each tile it then
 //   * re-tests only the block's near stars: those far from the tile join
 //     its polynomial, the rest are summed directly,
 //   * evaluates the polynomial for its rays (Horner), adds the near stars
@@ -48,9 +47,11 @@ constexpr int kTile = kLanesX * kCX;  // 64 rays per tile side
 constexpr int kManyStars = 65536;     // from here on, two workgroups per compute unit
 static_assert(kLanesX * kCX == kLanesY * kCY, "square tiles");
 
+constexpr int kMaxTiles = 16;         // tiles per workgroup block, at most 4 x 4
+
 struct ExpShared {
     double2 A[kOrder + 1];                      // the block's coefficients
-    double2 B[kOrder + 1];                      // the current tile's coefficients
+    double2 B[kMaxTiles][kOrder + 1];           // each tile's coefficients (blocks of more than one tile)
     double2 part[kWaves][kOrder + 1];           // per-wave partial sums
     int outer_idx[kWaves][kNearPerWave];        // the block's near stars, each wave's in index order
     int outer_n[kWaves];
@@ -74,7 +75,13 @@ __device__ __forceinline__ void region(const ShootParams &p, int64_t i, int64_t 
     cy = 0.5 * (y_first + y_last);
     const double hx = 0.5 * (x_last - x_first), hy = 0.5 * (y_last - y_first);
     rho = __builtin_sqrt(hx * hx + hy * hy) * (1.0 + 1e-12) + 1e-290;
-    // the same in every lane: keep them in scalar registers
+}
+
+// region() for a square every lane of the wave shares: the results are
+// moved to scalar registers.
+__device__ __forceinline__ void region_uniform(const ShootParams &p, int64_t i, int64_t j, int w, double &cx,
+                                               double &cy, double &rho) {
+    region(p, i, j, w, cx, cy, rho);
     cx = uniform_f64(cx);
     cy = uniform_f64(cy);
     rho = uniform_f64(rho);
@@ -171,17 +178,31 @@ __device__ __forceinline__ void reduce_coeffs(double2 (&acc)[kOrder + 1], ExpSha
     __syncthreads();
 }
 
+// Binomial coefficients C(n, k) for n, k <= kOrder: exact integers (at most
+// C(24, 12)) built by Pascal's rule at compile time.
+struct BinomialTable {
+    double c[kOrder + 1][kOrder + 1];
+};
+
+constexpr BinomialTable make_binomials() {
+    BinomialTable t{};
+    for (int n = 0; n <= kOrder; ++n) {
+        t.c[n][0] = 1.0;
+        for (int k = 1; k <= n; ++k) t.c[n][k] = t.c[n - 1][k - 1] + (k < n ? t.c[n - 1][k] : 0.0);
+    }
+    return t;
+}
+
+__constant__ BinomialTable kBinomial = make_binomials();
+
 // Coefficient r of the block's polynomial re-centred on a tile: with
 // s = a + b s' (a = (c - C) / R, b = rho / R),
 //   B_r = b^r sum_{q=r}^{kOrder} A_q C(q, r) a^(q - r),
-// summed by Horner in a from q = kOrder down.  The binomials are exact
-// integers (at most C(24, 12)), built by exact integer steps.
+// summed by Horner in a from q = kOrder down.
 __device__ __forceinline__ double2 shift_coeff(const double2 *A, int r, double2 a, double b) {
-    double c = 1.0;   // C(kOrder, r)
-    for (int i = 1; i <= r; ++i) c = (c * (double)(kOrder - r + i)) / (double)i;
-    double2 acc = make_double2(A[kOrder].x * c, A[kOrder].y * c);
+    double2 acc = make_double2(A[kOrder].x * kBinomial.c[kOrder][r], A[kOrder].y * kBinomial.c[kOrder][r]);
     for (int q = kOrder - 1; q >= r; --q) {
-        c = (c * (double)(q + 1 - r)) / (double)(q + 1);   // C(q, r) from C(q + 1, r)
+        const double c = kBinomial.c[q][r];
         const double2 t = cmul(acc, a);
         acc = make_double2(t.x + A[q].x * c, t.y + A[q].y * c);
     }
@@ -234,7 +255,7 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
 
     // --- the block: far stars into A, near stars into the outer lists
     double bcx, bcy, brho;
-    region(p, b_i, b_j, kTile * L, bcx, bcy, brho);
+    region_uniform(p, b_i, b_j, kTile * L, bcx, bcy, brho);
     {
         double2 acc[kOrder + 1];
 #pragma unroll
@@ -250,6 +271,18 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
         overflow |= ex.outer_n[w] > kNearPerWave;
         n_outer += ex.outer_n[w];
     }
+    if (L > 1 && !overflow) {   // uniform
+        // the block's polynomial re-centred on every tile at once
+        const double inv_brho = 1.0 / brho;
+        for (int idx = threadIdx.x; idx < L * L * (kOrder + 1); idx += kThreads) {
+            const int t = idx / (kOrder + 1), r = idx % (kOrder + 1);
+            double cx, cy, rho;
+            region(p, b_i + (int64_t)(t % L) * kTile, b_j + (int64_t)(t / L) * kTile, kTile, cx, cy, rho);
+            ex.B[t][r] = shift_coeff(ex.A, r, make_double2((cx - bcx) * inv_brho, (cy - bcy) * inv_brho),
+                                     rho * inv_brho);
+        }
+        __syncthreads();
+    }
 
     for (int t = 0; t < L * L; ++t) {   // uniform trip count
         const int64_t tile_i = b_i + (int64_t)(t % L) * kTile;
@@ -258,29 +291,25 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
 
         const int(*near_idx)[kNearPerWave] = ex.outer_idx;
         const int *near_n = ex.outer_n;
+        const double2 *coef = ex.B[L == 1 ? 0 : t];
         double cx = bcx, cy = bcy, rho = brho;
-        if (!overflow) {   // uniform
-            if constexpr (L == 1) {
-                if (threadIdx.x <= kOrder) ex.B[threadIdx.x] = ex.A[threadIdx.x];
-            } else {
-                region(p, tile_i, tile_j, kTile, cx, cy, rho);
-                const double inv_brho = 1.0 / brho;
-                if (threadIdx.x <= kOrder)
-                    ex.B[threadIdx.x] = shift_coeff(ex.A, threadIdx.x,
-                                                    make_double2((cx - bcx) * inv_brho, (cy - bcy) * inv_brho),
-                                                    rho * inv_brho);
-                double2 acc[kOrder + 1];
-#pragma unroll
-                for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
-                const double r_near = rho * inv_theta;
-                p2l_pass<true>(st, uniform(n_outer), ex.outer_idx, ex.outer_n, cx, cy, rho,
-                               uniform_f64(r_near * r_near), acc, ex.inner_idx, ex.inner_n);
-                __syncthreads();                        // B is written before it is added to
-                reduce_coeffs<true>(acc, ex, ex.B);     // its barriers also publish inner_n
-                near_idx = ex.inner_idx;
-                near_n = ex.inner_n;
-            }
+        if (L == 1 && !overflow) {   // uniform
+            // a copy per tile: read from a buffer the loop writes, the
+            // coefficients stay in LDS instead of 100 VGPRs
+            if (threadIdx.x <= kOrder) ex.B[0][threadIdx.x] = ex.A[threadIdx.x];
             __syncthreads();
+        }
+        if (L > 1 && !overflow) {   // uniform
+            region_uniform(p, tile_i, tile_j, kTile, cx, cy, rho);
+            double2 acc[kOrder + 1];
+#pragma unroll
+            for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
+            const double r_near = rho * inv_theta;
+            p2l_pass<true>(st, uniform(n_outer), ex.outer_idx, ex.outer_n, cx, cy, rho,
+                           uniform_f64(r_near * r_near), acc, ex.inner_idx, ex.inner_n);
+            reduce_coeffs<true>(acc, ex, ex.B[t]);   // its barriers also publish inner_n
+            near_idx = ex.inner_idx;
+            near_n = ex.inner_n;
         }
 
         double tx[kCX], ty[kCY];
@@ -299,7 +328,7 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
             for (int a = 0; a < kCX; ++a) wx[a] = (tx[a] - cx) * inv_rho;
 #pragma unroll
             for (int b = 0; b < kCY; ++b) wy[b] = (ty[b] - cy) * inv_rho;
-            const double2 top = ex.B[kOrder];
+            const double2 top = coef[kOrder];
 #pragma unroll
             for (int b = 0; b < kCY; ++b)
 #pragma unroll
@@ -308,7 +337,7 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
                     ay[b][a] = top.y;
                 }
             for (int q = kOrder - 1; q >= 0; --q) {
-                const double2 bq = ex.B[q];
+                const double2 bq = coef[q];
 #pragma unroll
                 for (int b = 0; b < kCY; ++b)
 #pragma unroll
