@@ -20,7 +20,9 @@
 // writes one.  Consecutive lanes take consecutive samples of one track, so
 // a wave's reads fall on a few neighbouring rows of the map, which stays in
 // L2 (a 1024^2 FP64 map is 8 MiB).  Its HBM traffic is the curves written
-// plus the map read once.
+// plus the map read once.  The curves are written with non-temporal
+// (streaming) stores: they are not read again by the kernel, and held in the
+// caches they would take the room and the bandwidth the map's lines need.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kLcThreads) void light_curve_kernel(
         const double r0v = m00[e] + fx[e] * (m01[e] - m00[e]);
         const double r1v = m10[e] + fx[e] * (m11[e] - m10[e]);
         const double val = r0v + fy[e] * (r1v - r0v);
-        if (live[e]) out[t[e] * n_samples + k[e]] = inside[e] ? val : __builtin_nan("");
+        if (live[e]) __builtin_nontemporal_store(inside[e] ? val : __builtin_nan(""), out + t[e] * n_samples + k[e]);
     }
 }
 
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(kLcThreads, 8) void light_curve_track_kernel(
         const double r0v = m00[e] + fx[e] * (m01[e] - m00[e]);
         const double r1v = m10[e] + fx[e] * (m11[e] - m10[e]);
         const double val = r0v + fy[e] * (r1v - r0v);
-        if (k < n_samples) row[k] = inside[e] ? val : __builtin_nan("");
+        if (k < n_samples) __builtin_nontemporal_store(inside[e] ? val : __builtin_nan(""), row + k);
     }
 }
 

@@ -96,6 +96,29 @@ def dispatch_waves(db, name_like, grid=None):
     return None
 
 
+def pmc_lines(dbs, kernel, grid, n_cu):
+    """Every counter of the kernel's dispatches in the given databases (mean
+    per dispatch, summed over hardware instances), and for counters of
+    cycles (busy, stall) their share of the CUs' cycles: value / (n_cu x the
+    dispatch's GRBM_GUI_ACTIVE per XCD)."""
+    vals, cycles = {}, None
+    for db in dbs:
+        for k, v in counter_values(db, kernel, grid).items():
+            vals[k] = sum(v) / len(v)
+        g = per_instance_mean(db, kernel, "GRBM_GUI_ACTIVE", grid)
+        if g:
+            cycles = g
+    out = ["memory-pipeline counters per dispatch (sum over instances):"]
+    for k in sorted(vals):
+        line = f"  {k}: {vals[k]:.4e}"
+        if cycles and k != "GRBM_GUI_ACTIVE" and ("BUSY" in k or "STALL" in k):
+            line += f"  ({vals[k] / (n_cu * cycles):.3f} of {n_cu} CUs' cycles)"
+        out.append(line)
+    if cycles:
+        out.append(f"cycles_per_dispatch: {cycles:.4e}  (GRBM_GUI_ACTIVE per XCD)")
+    return out
+
+
 def read_summary(path):
     """key: value pairs of a summary file (None if missing)."""
     if not os.path.exists(path):
@@ -122,6 +145,10 @@ def main(argv=None):
     ap.add_argument("--flop-per-launch", type=float, default=None)
     ap.add_argument("--grid", type=int, default=None,
                     help="only dispatches of this grid size (threads) give the kernel's time")
+    ap.add_argument("--pmc", nargs="*", default=[],
+                    help="more --pmc databases: every counter of the kernel is listed, and those counted in "
+                         "cycles also as a fraction of the CUs' cycles (GRBM_GUI_ACTIVE in one of them)")
+    ap.add_argument("--n-cu", type=int, default=256)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
@@ -197,6 +224,8 @@ def main(argv=None):
             if a.flop_per_launch:
                 lines.append(f"algorithmic_flop_per_launch: {a.flop_per_launch:.6e}")
                 lines.append(f"counter_over_algorithmic: {f64 / a.flop_per_launch:.4f}")
+    if a.pmc:
+        lines += [""] + pmc_lines(a.pmc, a.kernel, a.grid, a.n_cu)
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
