@@ -108,6 +108,49 @@ def test_light_curves_large_workload(torch):
     assert abs(float(curves.mean()) / float(mu.mean()) - 1) < 0.05
 
 
+def test_light_curves_maximum_sizes(torch, small_map):
+    """The largest sample count a track may have (2^24) in the track kernel,
+    and 2^20 tracks of 63 samples in the one-lane-per-sample kernel, with and
+    without the track order: sampled outputs are bit-identical to the
+    oracle's."""
+    w, counts, _, norm = small_map
+    mu, grid = R.source_map(counts, w.pix, norm, "gaussian", 2.0 * w.pix.Px)
+    host_mu = mu.cpu().numpy()
+    x0, y0, px, py, nx, ny = grid
+    xl, xh = x0 + 0.5 * px, x0 + (nx - 0.5) * px
+    yl, yh = y0 + 0.5 * py, y0 + (ny - 0.5) * py
+    ym = 0.5 * (yl + yh)
+    # two tracks of 2^24 samples: corner to corner, and one that leaves the map
+    xa, ya = np.array([xl, xl - 2 * px]), np.array([yl, ym])
+    xb, yb = np.array([xh, xh + 2 * px]), np.array([yh, ym + 3 * py])
+    n = 1 << 24
+    _say("light curves: 2 tracks x 2^24 samples")
+    got = R.light_curves(mu, grid, *(torch.from_numpy(a).cuda() for a in (xa, ya, xb, yb)), n)
+    rng = np.random.default_rng(11)
+    ks = np.unique(np.concatenate([[0, 1, 255, 256, 257, n - 257, n - 256, n - 2, n - 1],
+                                   rng.integers(0, n, 3000)]))
+    u, v = OL.sample_indices(grid, xa, ya, xb, yb, n)
+    want = OL.interpolate_indices(host_mu, u[:, ks], v[:, ks])
+    g = got[:, torch.as_tensor(ks, device="cuda")].cpu().numpy()
+    np.testing.assert_array_equal(np.isnan(g), np.isnan(want))
+    np.testing.assert_array_equal(g, want)
+    assert np.isfinite(g[0]).all() and np.isnan(g[1]).any() and np.isfinite(g[1]).any()
+    del got
+    # 2^20 short tracks: the kernel that takes one lane per sample
+    n_tracks, n_short = 1 << 20, 63
+    tracks = W.light_curve_tracks(grid, n_tracks, 1.5, seed=77)
+    dev = [torch.from_numpy(a).cuda() for a in tracks]
+    _say("light curves: 2^20 tracks x 63 samples")
+    plain = R.light_curves(mu, grid, *dev, n_short)
+    order, srt = R.track_order(grid, *dev, sorted_end_points=True)
+    ordered = R.light_curves(mu, grid, *dev, n_short, order=order, sorted=srt)
+    assert bool(torch.isfinite(plain).all())
+    assert torch.equal(plain, ordered)
+    sel = rng.integers(0, n_tracks, 300)
+    want = OL.light_curves(host_mu, grid, *(a[sel] for a in tracks), n_short)
+    np.testing.assert_array_equal(plain[torch.as_tensor(sel, device="cuda")].cpu().numpy(), want)
+
+
 def test_source_map_and_light_curve_errors(torch, small_map):
     w, counts, _, norm = small_map
     with pytest.raises(R.RayshError):
