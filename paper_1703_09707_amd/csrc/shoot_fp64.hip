@@ -95,9 +95,9 @@ __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, co
     if (k + NS <= k1) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            sx[s] = st[k + s].x;
-            sy[s] = st[k + s].y;
-            sm[s] = st[k + s].m;
+            asm volatile("" : "=s"(sx[s]) : "0"(st[k + s].x));
+            asm volatile("" : "=s"(sy[s]) : "0"(st[k + s].y));
+            asm volatile("" : "=s"(sm[s]) : "0"(st[k + s].m));
         }
     }
     for (; k + NS <= k1; k += NS) {
@@ -109,6 +109,7 @@ __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, co
             ny[s] = st[kn + s].y;
             nm[s] = st[kn + s].m;
         }
+        __builtin_amdgcn_sched_barrier(0);   // the loads stay ahead of the body
         // per column: the x offset and (FOLD) the offset times the mass;
         // per row: the square of the y offset and the y offset (times the mass)
         double ex[NS][CX], mex[NS][CX], ey2[NS][CY], mey[NS][CY];
@@ -151,9 +152,12 @@ __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, co
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            sx[s] = nx[s];
-            sy[s] = ny[s];
-            sm[s] = nm[s];
+            // an opaque hand-over: the prefetched records must be in their
+            // scalar registers here, at the end of the body, and cannot be
+            // reloaded next to their first use
+            asm volatile("" : "=s"(sx[s]) : "0"(nx[s]));
+            asm volatile("" : "=s"(sy[s]) : "0"(ny[s]));
+            asm volatile("" : "=s"(sm[s]) : "0"(nm[s]));
         }
     }
     for (; k < k1; ++k) {   // remaining stars, one at a time, still in index order
