@@ -148,32 +148,46 @@ __device__ __forceinline__ void p2l_pass(const ConstStar *st, int count, const i
 }
 
 // Workgroup sum of the lanes' coefficients into dst (added to it when ADD),
-// in a fixed order: a cross-lane tree in each wave, then the waves in turn.
+// in a fixed order.  Within a wave the 2 (kOrder + 1) real components,
+// padded with zeros to 64 slots, are reduced by recursive halving: at the
+// step of lane mask m, lanes with that bit keep the upper half of their
+// slots and the others the lower half, each adds the half its partner
+// sends, so after six steps lane l holds the wave's sum of slot l (126
+// exchanges per lane instead of 300 for a butterfly over every slot).
+// The waves' sums are then added in turn.
 template <bool ADD>
 __device__ __forceinline__ void reduce_coeffs(double2 (&acc)[kOrder + 1], ExpShared &ex, double2 *dst) {
+    constexpr int kSlots = 2 * (kOrder + 1);
+    static_assert(kSlots <= 64, "one slot per lane at the end");
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    double v[64];
 #pragma unroll
     for (int q = 0; q <= kOrder; ++q) {
-        double vx = acc[q].x, vy = acc[q].y;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            vx += __shfl_xor(vx, off, 64);
-            vy += __shfl_xor(vy, off, 64);
-        }
-        if (lane == 0) ex.part[wave][q] = make_double2(vx, vy);
+        v[2 * q] = acc[q].x;
+        v[2 * q + 1] = acc[q].y;
     }
+#pragma unroll
+    for (int i = kSlots; i < 64; ++i) v[i] = 0.0;
+#pragma unroll
+    for (int n = 64; n > 1; n /= 2) {
+        const int m = n / 2;                 // the lane bit of this step
+        const bool upper = (lane & m) != 0;
+#pragma unroll
+        for (int i = 0; i < n / 2; ++i) {
+            const double keep = upper ? v[i + n / 2] : v[i];
+            const double send = upper ? v[i] : v[i + n / 2];
+            v[i] = keep + __shfl_xor(send, m, 64);
+        }
+    }
+    double *part = reinterpret_cast<double *>(&ex.part[wave][0]);
+    if (lane < kSlots) part[lane] = v[0];
     __syncthreads();
-    if (threadIdx.x <= kOrder) {
-        double2 s = ex.part[0][threadIdx.x];
-        for (int w = 1; w < kWaves; ++w) {
-            s.x += ex.part[w][threadIdx.x].x;
-            s.y += ex.part[w][threadIdx.x].y;
-        }
-        if (ADD) {
-            s.x += dst[threadIdx.x].x;
-            s.y += dst[threadIdx.x].y;
-        }
-        dst[threadIdx.x] = s;
+    if (threadIdx.x < kSlots) {
+        double t = reinterpret_cast<const double *>(&ex.part[0][0])[threadIdx.x];
+        for (int w = 1; w < kWaves; ++w) t += reinterpret_cast<const double *>(&ex.part[w][0])[threadIdx.x];
+        double *d = reinterpret_cast<double *>(dst);
+        if (ADD) t += d[threadIdx.x];
+        d[threadIdx.x] = t;
     }
     __syncthreads();
 }
