@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--no-light-curves", action="store_true", help="skip the light-curve timing")
     ap.add_argument("--no-lc-given-order", action="store_true",
                     help="time light curves in the track order only (not also in the given order)")
-    ap.add_argument("--cpu-rays", type=int, default=768, help="side of the oracle's ray sample")
+    ap.add_argument("--cpu-rays", type=int, default=1024, help="side of the oracle's ray sample (about 15 s)")
     ap.add_argument("--cpu-all-rays", type=int, default=2048,
                     help="side of the ray sample of the all-cores oracle run")
     ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
