@@ -161,6 +161,30 @@ int raysh_set_expansion(raysh_ctx *ctx, double theta_open);
  * EINVAL for a NULL context or a block other than 0, 1, 2 or 4. */
 int raysh_set_expansion_block(raysh_ctx *ctx, int block);
 
+/* Star cells of RAYSH_FP64_EXPANSION's block pass.  With cells, the stars
+ * are sorted once (per context, on the first call that uses them) by the
+ * cell of a regular grid over their bounding box, and each cell gets a
+ * multipole expansion of its stars (order raysh_expansion_order(), scaled by
+ * the cell's radius r_c).  A cell whose centre lies at least
+ * (r_c + rho) / theta_open from a block's centre enters the block's local
+ * expansion through it (a multipole-to-local translation: exact algebra
+ * up to truncation at the same order and the same error bound per cell);
+ * the stars of the other cells are tested one by one as without cells.
+ * This is the cell expansion of distant stars that the tree codes of the
+ * paper's Sec. 1 rest on.  The near stars are the same with or without
+ * cells; their direct sums then go in cell order (index order within a
+ * cell) instead of index order.
+ *   RAYSH_CELLS_AUTO (default): cells from 65536 stars on (below that the
+ *     block pass is a small share of the time, and the translations' registers
+ *     would cost the kernel a third workgroup per compute unit).
+ *   RAYSH_CELLS_ALWAYS: cells whenever the stars span a nonzero box.
+ *   RAYSH_CELLS_NEVER: the block pass expands every far star on its own.
+ * The grid has at most 4096 cells and 256 rows and columns; building it
+ * copies the stars to the host (two copies; at most 2^26 stars, beyond
+ * which no cells are used).  EINVAL for a NULL context or another mode. */
+enum { RAYSH_CELLS_AUTO = 0, RAYSH_CELLS_ALWAYS = 1, RAYSH_CELLS_NEVER = 2 };
+int raysh_set_expansion_cells(raysh_ctx *ctx, int mode);
+
 /* Number of Taylor terms minus one (the order) of RAYSH_FP64_EXPANSION. */
 int raysh_expansion_order(void);
 

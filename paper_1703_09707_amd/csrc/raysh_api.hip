@@ -23,6 +23,7 @@ constexpr int64_t kMaxRays = std::numeric_limits<int32_t>::max();
 constexpr int64_t kMaxIndex = int64_t(1) << 53;
 
 constexpr size_t kMaxSplitBytes = size_t(2) << 30;   // automatic split-K workspace cap
+constexpr int64_t kCellAutoStars = 65536;             // star cells by default from this many stars on
 constexpr int kMinStarsPerPart = 64;
 
 // Parts of the FP64 star sum for this call (1 = one pass).
@@ -68,8 +69,23 @@ int launch(raysh_ctx *c, const ShootParams &p, int precision, const char *what) 
     } else if (precision == RAYSH_FP32_BULK) {
         e = raysh::launch_shoot_fp32(p, c->shape[1], c->stream);
     } else {
+        raysh::StarCells cells{};   // ncx = 0: the block pass visits every star
+        const bool want = c->expansion_cells == RAYSH_CELLS_ALWAYS ||
+                          (c->expansion_cells == RAYSH_CELLS_AUTO && c->n_stars >= kCellAutoStars);
+        if (want) {
+            if (!c->cells_built) {
+                e = raysh::build_star_cells(c->d_stars, c->n_stars, c->stream, c->cells);
+                if (e == hipErrorOutOfMemory) {
+                    (void)hipGetLastError();
+                    return set_error(RAYSH_ENOMEM, "%s: star cells of %lld stars", what, (long long)c->n_stars);
+                }
+                if (e != hipSuccess) return hip_error(e, what);
+                c->cells_built = true;
+            }
+            cells = c->cells.view;
+        }
         e = raysh::launch_shoot_expansion(
-            p, c->theta_open,
+            p, cells, c->theta_open,
             c->expansion_block ? c->expansion_block : raysh::expansion_block(p.nx, p.ny, c->n_stars, c->n_cu),
             c->stream);
     }
@@ -301,6 +317,14 @@ int raysh_set_expansion(raysh_ctx *ctx, double theta_open) {
     return set_ok();
 }
 
+int raysh_set_expansion_cells(raysh_ctx *ctx, int mode) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "raysh_set_expansion_cells: NULL context");
+    if (mode != RAYSH_CELLS_AUTO && mode != RAYSH_CELLS_ALWAYS && mode != RAYSH_CELLS_NEVER)
+        return set_error(RAYSH_EINVAL, "expansion cells mode must be RAYSH_CELLS_AUTO, _ALWAYS or _NEVER");
+    ctx->expansion_cells = mode;
+    return set_ok();
+}
+
 int raysh_set_expansion_block(raysh_ctx *ctx, int block) {
     if (!ctx) return set_error(RAYSH_EINVAL, "raysh_set_expansion_block: NULL context");
     if (block != 0 && block != 1 && block != 2 && block != 4)
@@ -455,6 +479,7 @@ int raysh_free(raysh_ctx *ctx) {
         if (ctx->d_counter) (void)hipFree(ctx->d_counter);
         if (ctx->d_partial) (void)hipFree(ctx->d_partial);
         if (ctx->h_counter) (void)hipHostFree(ctx->h_counter);
+        raysh::free_star_cells(ctx->cells);
     }
     delete ctx;
     if (code != RAYSH_OK) return set_error(code, "raysh_free: pending device error");

@@ -18,6 +18,9 @@ struct raysh_ctx {
     int star_parts = 1;                    // FP64 split of each ray's star sum (0 = automatic)
     double theta_open = 0.25;              // far-star criterion of RAYSH_FP64_EXPANSION
     int expansion_block = 0;               // tiles per side of its workgroups (0 = automatic)
+    int expansion_cells = RAYSH_CELLS_AUTO;   // star cells of its block pass
+    bool cells_built = false;
+    raysh::StarCellStore cells;            // built on the first call that uses them
     double2 *d_partial = nullptr;          // split-K workspace
     size_t partial_bytes = 0;
     int n_cu = 0;

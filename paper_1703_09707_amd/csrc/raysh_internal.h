@@ -83,10 +83,39 @@ hipError_t launch_batch_fp32(const BatchArgs &b, const TileShape &shape, int blo
 int batch_fp64_blocks_per_cu(const TileShape &shape);
 int batch_fp32_blocks_per_cu(const TileShape &shape);
 
+// Cells of the star field for the expansion mode: the star records sorted
+// by the cell of a regular grid (origin gx0, gy0, side h; cell c = j ncx + i),
+// with each cell's scaled multipole expansion.  ncx = 0: no cells.
+struct StarCells {
+    const Star *sorted;        // star records by cell; pad holds the star's index (int64 bits)
+    const int32_t *start;      // [ncx * ncy + 1]: first record of each cell
+    const double2 *mult;       // [ncx * ncy][expansion_order() + 1]
+    double gx0, gy0, h, rc;    // rc: radius around a cell's centre that holds its stars
+    int32_t ncx, ncy;
+};
+
+// Device buffers behind a StarCells view (owned by a context).
+struct StarCellStore {
+    StarCells view{};
+    Star *sorted = nullptr;
+    int32_t *start = nullptr;
+    double2 *mult = nullptr;
+};
+
+// Builds the cells of n_stars device star records (host sort, device
+// multipoles; synchronous on s).  Leaves out.view.ncx = 0 when cells do not
+// apply (fewer than 2 stars, all at one point, or more than the host build
+// takes).  Returns the first HIP error.
+hipError_t build_star_cells(const Star *d_stars, int64_t n_stars, hipStream_t s, StarCellStore &out);
+void free_star_cells(StarCellStore &cells);
+
 // FP64 with the far field as local expansions (shoot_expansion.hip); tiles
 // of 64 x 64 rays, one workgroup per block of `block` x `block` tiles
-// (1, 2 or 4).  expansion_block picks the block for a lattice block.
-hipError_t launch_shoot_expansion(const ShootParams &p, double theta_open, int block, hipStream_t s);
+// (1, 2 or 4).  expansion_block picks the block for a lattice block.  With
+// cells (cells.ncx > 0) the block pass takes distant cells through their
+// multipole expansions.
+hipError_t launch_shoot_expansion(const ShootParams &p, const StarCells &cells, double theta_open, int block,
+                                  hipStream_t s);
 int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu);
 int expansion_order();
 

@@ -32,6 +32,8 @@
 // block has more near stars than its lists hold, its tiles sum every star
 // directly.
 #include <algorithm>
+#include <cmath>
+#include <vector>
 
 #include "ray_common.h"
 
@@ -48,6 +50,10 @@ constexpr int kManyStars = 65536;     // from here on, two workgroups per comput
 static_assert(kLanesX * kCX == kLanesY * kCY, "square tiles");
 
 constexpr int kMaxTiles = 16;         // tiles per workgroup block, at most 4 x 4
+constexpr int kCellMaxRows = kThreads;   // star-cell grid rows and columns: one thread per row
+constexpr int kCellMaxCells = 4096;
+constexpr int64_t kCellMaxStars = int64_t(1) << 26;   // the host keeps two copies while building
+constexpr int32_t kCellMaxPerCell = 1 << 20;          // stars of one cell (its multipoles take one thread)
 
 struct ExpShared {
     double2 A[kOrder + 1];                      // the block's coefficients
@@ -57,6 +63,10 @@ struct ExpShared {
     int outer_n[kWaves];
     int inner_idx[kWaves][kNearPerWave];        // the tile's near stars (a subset of the block's)
     int inner_n[kWaves];
+    int row_lo[kCellMaxRows], row_hi[kCellMaxRows];   // each star-cell row's band of open cells
+    int row_first[kCellMaxRows];                      // first record of the band's stars
+    int row_pref[kCellMaxRows];                       // the bands' stars before this row
+    int wave_tot[kWaves];
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -87,40 +97,27 @@ __device__ __forceinline__ void region_uniform(const ShootParams &p, int64_t i, 
     rho = uniform_f64(rho);
 }
 
-// One pass over `count` stars split into four contiguous quarters, one per
-// wave.  Entry e is star e (LIST false) or the e-th entry of the
-// concatenated per-wave lists in_idx / in_n (LIST true).  A star farther
-// than sqrt(r_near2) from (cx, cy) adds m u (-u rho)^q to the lane's
-// coefficients; a nearer one is appended to its wave's out list, so that
-// the concatenated out lists stay in star index order.  out_n counts every
-// near star, also beyond the capacity.
-template <bool LIST>
-__device__ __forceinline__ void p2l_pass(const ConstStar *st, int count, const int (*in_idx)[kNearPerWave],
-                                         const int *in_n, double cx, double cy, double rho, double r_near2,
+// One pass over `count` entries split into four contiguous quarters, one per
+// wave.  fetch(e, k, x, y, m) gives entry e's star: its index k and record.
+// A star farther than sqrt(r_near2) from (cx, cy) adds m u (-u rho)^q to
+// the lane's coefficients; a nearer one is appended to its wave's out list,
+// so that the concatenated out lists keep the entries' order.  out_n counts
+// every near star, also beyond the capacity.
+template <class Fetch>
+__device__ __forceinline__ void p2l_pass(int count, Fetch fetch, double cx, double cy, double rho, double r_near2,
                                          double2 (&acc)[kOrder + 1], int (*out_idx)[kNearPerWave], int *out_n) {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int per_wave = (count + kWaves - 1) / kWaves;
     const int w0 = wave * per_wave < count ? wave * per_wave : count;
     const int w1 = w0 + per_wave < count ? w0 + per_wave : count;
-    int n0 = 0, n1 = 0, n2 = 0;
-    if (LIST) {
-        n0 = in_n[0];
-        n1 = n0 + in_n[1];
-        n2 = n1 + in_n[2];
-    }
     int found = 0;   // this wave's near stars so far (uniform in the wave)
     for (int base = w0; base < w1; base += 64) {
         const int e = base + lane;
         bool near = false;
         int k = 0;
         if (e < w1) {
-            if (LIST) {
-                k = e < n0 ? in_idx[0][e] : e < n1 ? in_idx[1][e - n0] : e < n2 ? in_idx[2][e - n1]
-                                                                                : in_idx[3][e - n2];
-            } else {
-                k = e;
-            }
-            const double sx = st[k].x, sy = st[k].y, sm = st[k].m;
+            double sx, sy, sm;
+            fetch(e, k, sx, sy, sm);
             const double dx = cx - sx, dy = cy - sy;
             const double d2 = dx * dx + dy * dy;
             near = d2 <= r_near2;
@@ -145,6 +142,71 @@ __device__ __forceinline__ void p2l_pass(const ConstStar *st, int count, const i
         found += __popcll(ball);
     }
     if (lane == 0) out_n[wave] = found;
+}
+
+// Binomial coefficients C(j + q, q) for j, q <= kOrder: exact integers (at
+// most C(48, 24) < 2^53) built by Pascal's rule at compile time.
+struct CellBinomialTable {
+    double c[kOrder + 1][kOrder + 1];
+};
+
+constexpr CellBinomialTable make_cell_binomials() {
+    CellBinomialTable t{};
+    for (int j = 0; j <= kOrder; ++j)
+        for (int q = 0; q <= kOrder; ++q)
+            t.c[j][q] = (j == 0 || q == 0) ? 1.0 : t.c[j - 1][q] + t.c[j][q - 1];
+    return t;
+}
+
+__constant__ CellBinomialTable kCellBinomial = make_cell_binomials();
+
+// A star cell's multipole expansion (scaled: M_j = sum_k m_k ((z_k - z_c) / r_c)^j)
+// translated to the local expansion of a region of centre C and radius
+// rho, added to acc.  With D = C - z_c, w = 1/D and g = -rho w,
+//   sum_k m_k / (C + rho s - z_k) = w sum_j M_j (r_c w)^j sum_q C(j + q, q) g^q s^q,
+// which converges for (r_c + rho) < |D| and, truncated at kOrder in j and
+// q, leaves at most theta^(kOrder+1) / (1 - theta) of the cell's field with
+// theta = (r_c + rho) / |D|, the bound of the per-star expansion.
+__device__ __forceinline__ void m2l_cell(const double2 *M, double dx, double dy, double rc, double rho,
+                                         double2 (&acc)[kOrder + 1]) {
+    const double inv = 1.0 / (dx * dx + dy * dy);
+    const double2 w = make_double2(dx * inv, -dy * inv);
+    const double2 g = make_double2(-rho * w.x, -rho * w.y);
+    const double2 a = make_double2(rc * w.x, rc * w.y);
+    double2 ap = w;   // w (r_c w)^j
+    for (int j = 0; j <= kOrder; ++j) {   // uniform trip count
+        double2 t = cmul(M[j], ap);
+#pragma unroll
+        for (int q = 0; q <= kOrder; ++q) {
+            const double b = kCellBinomial.c[j][q];
+            acc[q].x = __builtin_fma(b, t.x, acc[q].x);
+            acc[q].y = __builtin_fma(b, t.y, acc[q].y);
+            if (q < kOrder) t = cmul(t, g);
+        }
+        ap = cmul(ap, a);
+    }
+}
+
+// Exclusive prefix sum of one int per thread over the workgroup (values of
+// threads past `n` count as zero); returns the thread's prefix and writes the
+// total to *total.  Every thread of the workgroup must call it.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *wave_tot, int *total) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int up = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += up;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) before += wave_tot[w];
+        all += wave_tot[w];
+    }
+    *total = all;
+    return before + incl - v;
 }
 
 // Workgroup sum of the lanes' coefficients into dst (added to it when ADD),
@@ -248,13 +310,84 @@ __device__ __forceinline__ void direct_star(const ConstStar *st, int k, const do
     }
 }
 
+// The block pass over star cells.  A cell whose centre is at least
+// (r_c + rho) / theta_open from the block's centre enters the block's
+// coefficients through its multipole expansion (m2l_cell); the rest form,
+// in each row of the cell grid, a band of open cells whose stars are tested
+// one by one as in the pass over every star, so the near lists hold the
+// same stars (in cell order, index order within a cell).
+__device__ __forceinline__ void block_pass_cells(const StarCells &cells, double bcx, double bcy, double brho,
+                                                 double inv_theta, double r_near2, double2 (&acc)[kOrder + 1],
+                                                 ExpShared &ex) {
+    const int ncx = uniform(cells.ncx), ncy = uniform(cells.ncy);
+    const double h = uniform_f64(cells.h), rc = uniform_f64(cells.rc);
+    const double gx0 = uniform_f64(cells.gx0), gy0 = uniform_f64(cells.gy0);
+    const double rmac = (rc + brho) * inv_theta;
+    const double rmac2 = rmac * rmac;
+    // row j (one thread each): its band [lo, hi] and the band's stars
+    const int j = threadIdx.x;
+    int first = 0, cnt = 0;
+    if (j < ncy) {
+        const double dy = bcy - (gy0 + ((double)j + 0.5) * h);
+        int lo = ncx, hi = -1;
+        for (int i = 0; i < ncx; ++i) {
+            const double dx = bcx - (gx0 + ((double)i + 0.5) * h);
+            if (dx * dx + dy * dy < rmac2) {
+                if (lo > i) lo = i;
+                hi = i;
+            }
+        }
+        ex.row_lo[j] = lo;
+        ex.row_hi[j] = hi;
+        if (hi >= lo) {
+            first = cells.start[j * ncx + lo];
+            cnt = cells.start[j * ncx + hi + 1] - first;
+        }
+        ex.row_first[j] = first;
+    }
+    int total = 0;
+    const int pref = block_exclusive_scan(cnt, ex.wave_tot, &total);   // its barrier publishes the bands
+    if (j < ncy) ex.row_pref[j] = pref;
+    __syncthreads();
+    // every non-empty cell outside the bands, through its multipole expansion
+    const int n_cells = ncx * ncy;
+    for (int c = threadIdx.x; c < n_cells; c += kThreads) {
+        const int i = c % ncx, jj = c / ncx;
+        if (i >= ex.row_lo[jj] && i <= ex.row_hi[jj]) continue;
+        if (cells.start[c + 1] == cells.start[c]) continue;
+        const double dx = bcx - (gx0 + ((double)i + 0.5) * h);
+        const double dy = bcy - (gy0 + ((double)jj + 0.5) * h);
+        m2l_cell(cells.mult + (size_t)c * (kOrder + 1), dx, dy, rc, brho, acc);
+    }
+    // the bands' stars, one by one: entry e is in the last row whose prefix
+    // is at most e (rows before it hold fewer stars, empty rows share their
+    // successor's prefix)
+    const Star *sorted = cells.sorted;
+    p2l_pass(
+        uniform(total),
+        [&](int e, int &k, double &x, double &y, double &m) {
+            int lo = 0, hi = ncy - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (ex.row_pref[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            const Star st = sorted[ex.row_first[lo] + (e - ex.row_pref[lo])];
+            x = st.x;
+            y = st.y;
+            m = st.m;
+            k = (int)__builtin_bit_cast(long long, st.pad);
+        },
+        bcx, bcy, brho, r_near2, acc, ex.outer_idx, ex.outer_n);
+}
+
 // WPS waves per SIMD (workgroups per compute unit): 3 suits few stars per
 // block, where the tiles' work dominates and more workgroups hide its
 // barriers; 2 suits many, where the pass over the stars dominates and
 // needs its registers (at 3 it spills a few values inside that loop).
-template <int L, int WPS>
-__global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootParams p, double theta_open,
-                                                                       int blocks_x) {
+template <int L, int WPS, bool CELLS>
+__global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootParams p, StarCells cells,
+                                                                       double theta_open, int blocks_x) {
     __shared__ BinShared sh;
     __shared__ ExpShared ex;
     bin_shared_init(sh);
@@ -275,8 +408,20 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
 #pragma unroll
         for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
         const double r_near = brho * inv_theta;
-        p2l_pass<false>(st, n, nullptr, nullptr, bcx, bcy, brho, uniform_f64(r_near * r_near), acc, ex.outer_idx,
-                        ex.outer_n);
+        const double r_near2 = uniform_f64(r_near * r_near);
+        if constexpr (CELLS) {
+            block_pass_cells(cells, bcx, bcy, brho, inv_theta, r_near2, acc, ex);
+        } else {
+            p2l_pass(
+                n,
+                [&](int e, int &k, double &x, double &y, double &m) {
+                    k = e;
+                    x = st[e].x;
+                    y = st[e].y;
+                    m = st[e].m;
+                },
+                bcx, bcy, brho, r_near2, acc, ex.outer_idx, ex.outer_n);
+        }
         reduce_coeffs<false>(acc, ex, ex.A);   // its barriers also publish outer_n
     }
     bool overflow = false;
@@ -319,8 +464,19 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
 #pragma unroll
             for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
             const double r_near = rho * inv_theta;
-            p2l_pass<true>(st, uniform(n_outer), ex.outer_idx, ex.outer_n, cx, cy, rho,
-                           uniform_f64(r_near * r_near), acc, ex.inner_idx, ex.inner_n);
+            const int n0 = ex.outer_n[0], n1 = n0 + ex.outer_n[1], n2 = n1 + ex.outer_n[2];
+            p2l_pass(
+                uniform(n_outer),
+                [&](int e, int &k, double &x, double &y, double &m) {
+                    k = e < n0   ? ex.outer_idx[0][e]
+                        : e < n1 ? ex.outer_idx[1][e - n0]
+                        : e < n2 ? ex.outer_idx[2][e - n1]
+                                 : ex.outer_idx[3][e - n2];
+                    x = st[k].x;
+                    y = st[k].y;
+                    m = st[k].m;
+                },
+                cx, cy, rho, uniform_f64(r_near * r_near), acc, ex.inner_idx, ex.inner_n);
             reduce_coeffs<true>(acc, ex, ex.B[t]);   // its barriers also publish inner_n
             near_idx = ex.inner_idx;
             near_n = ex.inner_n;
@@ -389,17 +545,53 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
     }
 }
 
+// Without cells: three workgroups per compute unit below kManyStars stars,
+// two from there on.  With cells the translations need the registers of
+// two (at three they would spill about 100 VGPRs).
 template <int L>
-hipError_t launch_level(const ShootParams &p, double theta_open, int64_t tiles_x, int64_t tiles_y,
-                        hipStream_t s) {
+hipError_t launch_level(const ShootParams &p, const StarCells &cells, double theta_open, int64_t tiles_x,
+                        int64_t tiles_y, hipStream_t s) {
     const int64_t bx = (tiles_x + L - 1) / L, by = (tiles_y + L - 1) / L;
-    if (p.n_stars < kManyStars)
-        hipLaunchKernelGGL((expansion_fp64_kernel<L, 3>), dim3((unsigned)(bx * by)), dim3(kThreads), 0, s, p,
-                           theta_open, (int)bx);
+    const dim3 grid((unsigned)(bx * by));
+    if (cells.ncx > 0)
+        hipLaunchKernelGGL((expansion_fp64_kernel<L, 2, true>), grid, dim3(kThreads), 0, s, p, cells, theta_open,
+                           (int)bx);
+    else if (p.n_stars < kManyStars)
+        hipLaunchKernelGGL((expansion_fp64_kernel<L, 3, false>), grid, dim3(kThreads), 0, s, p, cells, theta_open,
+                           (int)bx);
     else
-        hipLaunchKernelGGL((expansion_fp64_kernel<L, 2>), dim3((unsigned)(bx * by)), dim3(kThreads), 0, s, p,
-                           theta_open, (int)bx);
+        hipLaunchKernelGGL((expansion_fp64_kernel<L, 2, false>), grid, dim3(kThreads), 0, s, p, cells, theta_open,
+                           (int)bx);
     return hipGetLastError();
+}
+
+// Each star cell's scaled multipole expansion, one thread per cell, its
+// stars in their sorted order.
+__global__ __launch_bounds__(kThreads) void star_cell_multipole_kernel(const Star *__restrict__ sorted,
+                                                                      const int32_t *__restrict__ start, int ncx,
+                                                                      int ncy, double gx0, double gy0, double h,
+                                                                      double rc, double2 *__restrict__ mult) {
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= ncx * ncy) return;
+    const double cx = gx0 + ((double)(c % ncx) + 0.5) * h;
+    const double cy = gy0 + ((double)(c / ncx) + 0.5) * h;
+    const double inv = 1.0 / rc;
+    double2 acc[kOrder + 1];
+#pragma unroll
+    for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int i = start[c]; i < start[c + 1]; ++i) {
+        const Star st = sorted[i];
+        const double2 t = make_double2((st.x - cx) * inv, (st.y - cy) * inv);   // (z_k - z_c) / r_c
+        double2 tp = make_double2(st.m, 0.0);
+#pragma unroll
+        for (int q = 0; q <= kOrder; ++q) {
+            acc[q].x += tp.x;
+            acc[q].y += tp.y;
+            if (q < kOrder) tp = cmul(tp, t);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q <= kOrder; ++q) mult[(size_t)c * (kOrder + 1) + q] = acc[q];
 }
 
 }  // namespace
@@ -428,17 +620,107 @@ int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu) {
     return best;
 }
 
-hipError_t launch_shoot_expansion(const ShootParams &p, double theta_open, int block, hipStream_t s) {
+hipError_t launch_shoot_expansion(const ShootParams &p, const StarCells &cells, double theta_open, int block,
+                                  hipStream_t s) {
     ShootParams q = p;
     const int64_t tiles_x = (p.nx + kTile - 1) / kTile;
     const int64_t tiles_y = (p.ny + kTile - 1) / kTile;
     q.tiles_x = (int32_t)tiles_x;
     switch (block) {
-        case 1: return launch_level<1>(q, theta_open, tiles_x, tiles_y, s);
-        case 2: return launch_level<2>(q, theta_open, tiles_x, tiles_y, s);
-        case 4: return launch_level<4>(q, theta_open, tiles_x, tiles_y, s);
+        case 1: return launch_level<1>(q, cells, theta_open, tiles_x, tiles_y, s);
+        case 2: return launch_level<2>(q, cells, theta_open, tiles_x, tiles_y, s);
+        case 4: return launch_level<4>(q, cells, theta_open, tiles_x, tiles_y, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+void free_star_cells(StarCellStore &c) {
+    if (c.sorted) (void)hipFree(c.sorted);
+    if (c.start) (void)hipFree(c.start);
+    if (c.mult) (void)hipFree(c.mult);
+    c = StarCellStore{};
+}
+
+// The cell side balances a block's two costs: the stars of its open cells,
+// tested one by one (their number grows as side^2), against the
+// translations of the other cells (whose number falls as 1/side^2, each
+// about 26 times the work of one star's expansion).  Their sum is least
+// near side = sqrt(area / sqrt(N*)) for theta_open = 0.25; the grid is then
+// coarsened until it fits the workgroup's tables.
+hipError_t build_star_cells(const Star *d_stars, int64_t n_stars, hipStream_t s, StarCellStore &out) {
+    free_star_cells(out);
+    if (n_stars < 2 || n_stars > kCellMaxStars) return hipSuccess;   // no cells
+    std::vector<Star> host((size_t)n_stars);
+    hipError_t e = hipMemcpyAsync(host.data(), d_stars, (size_t)n_stars * sizeof(Star), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    double x0 = host[0].x, x1 = host[0].x, y0 = host[0].y, y1 = host[0].y;
+    for (const Star &st : host) {
+        x0 = std::min(x0, st.x);
+        x1 = std::max(x1, st.x);
+        y0 = std::min(y0, st.y);
+        y1 = std::max(y1, st.y);
+    }
+    const double w = x1 - x0, hgt = y1 - y0, big = std::max(w, hgt);
+    if (!(big > 0.0)) return hipSuccess;   // every star at one point: no cells
+    const double area = std::max(w * hgt, 1e-6 * big * big);
+    double side = std::sqrt(area / std::sqrt((double)n_stars));
+    int ncx = 0, ncy = 0;
+    for (;;) {
+        ncx = (int)std::min(std::floor(w / side) + 1.0, 1e9);
+        ncy = (int)std::min(std::floor(hgt / side) + 1.0, 1e9);
+        if (ncx <= kCellMaxRows && ncy <= kCellMaxRows && (int64_t)ncx * ncy <= kCellMaxCells) break;
+        side *= 1.25;
+    }
+    const int n_cells = ncx * ncy;
+    // counting sort of the stars by cell, index order within a cell
+    std::vector<int32_t> cell((size_t)n_stars), start((size_t)n_cells + 1, 0);
+    for (int64_t k = 0; k < n_stars; ++k) {
+        const int i = std::min((int)((host[k].x - x0) / side), ncx - 1);
+        const int j = std::min((int)((host[k].y - y0) / side), ncy - 1);
+        cell[k] = j * ncx + i;
+        ++start[cell[k] + 1];
+    }
+    int32_t most = 0;
+    for (int c = 0; c < n_cells; ++c) most = std::max(most, start[c + 1]);
+    if (most > kCellMaxPerCell) return hipSuccess;   // one thread per cell would take too long: no cells
+    for (int c = 0; c < n_cells; ++c) start[c + 1] += start[c];
+    std::vector<Star> sorted((size_t)n_stars);
+    {
+        std::vector<int32_t> fill(start.begin(), start.end() - 1);
+        for (int64_t k = 0; k < n_stars; ++k) {
+            Star st = host[k];
+            st.pad = __builtin_bit_cast(double, (long long)k);   // the star's index
+            sorted[fill[cell[k]]++] = st;
+        }
+    }
+    StarCellStore c;
+    e = hipMalloc(&c.sorted, (size_t)n_stars * sizeof(Star));
+    if (e == hipSuccess) e = hipMalloc(&c.start, ((size_t)n_cells + 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&c.mult, (size_t)n_cells * (kOrder + 1) * sizeof(double2));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c.sorted, sorted.data(), (size_t)n_stars * sizeof(Star), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c.start, start.data(), ((size_t)n_cells + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                           s);
+    // cells hold every star in the closed square of their cell (the last row
+    // and column also the stars on the far edge): r_c is the half-diagonal,
+    // enlarged for the rounding of the cell assignment
+    const double rc = side * std::sqrt(0.5) * (1.0 + 1e-12);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(star_cell_multipole_kernel, dim3((unsigned)((n_cells + kThreads - 1) / kThreads)),
+                           dim3(kThreads), 0, s, c.sorted, c.start, ncx, ncy, x0, y0, side, rc, c.mult);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host tables are released on return
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_star_cells(c);
+        return e;
+    }
+    c.view = StarCells{c.sorted, c.start, c.mult, x0, y0, side, rc, ncx, ncy};
+    out = c;
+    return hipSuccess;
 }
 
 }  // namespace raysh

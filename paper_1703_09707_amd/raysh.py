@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libraysh.so")
 FP64 = 0
 FP32_BULK = 1
 FP64_EXPANSION = 2
+CELL_MODES = {"auto": 0, "always": 1, "never": 2}   # RAYSH_CELLS_*
 PRECISIONS = {"fp64": FP64, "fp32_bulk": FP32_BULK, "fp64_expansion": FP64_EXPANSION,
               FP64: FP64, FP32_BULK: FP32_BULK, FP64_EXPANSION: FP64_EXPANSION}
 
@@ -31,7 +32,8 @@ OK, EINVAL, EOVERFLOW, ENOMEM, EDEVICE = 0, 1, 2, 3, 4
 _CODES = {EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"}
 
 EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", "raysh_set_star_split",
-           "raysh_set_expansion", "raysh_set_expansion_block", "raysh_expansion_order",
+           "raysh_set_expansion", "raysh_set_expansion_block", "raysh_set_expansion_cells",
+           "raysh_expansion_order",
            "raysh_list_tiles",
            "raysh_get_tile", "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch",
            "raysh_histogram_workspace", "raysh_log_mag_histogram",
@@ -97,6 +99,8 @@ def load():
     lib.raysh_set_expansion.restype = I
     lib.raysh_set_expansion_block.argtypes = [P, I]
     lib.raysh_set_expansion_block.restype = I
+    lib.raysh_set_expansion_cells.argtypes = [P, I]
+    lib.raysh_set_expansion_cells.restype = I
     lib.raysh_expansion_order.argtypes = []
     lib.raysh_expansion_order.restype = I
     lib.raysh_set_star_split.argtypes = [P, I]
@@ -236,6 +240,11 @@ class Context:
         """raysh_set_expansion_block: tiles per side of the expansion mode's
         workgroups (0 = automatic, 1, 2 or 4)."""
         check(load().raysh_set_expansion_block(self.handle, int(block)))
+
+    def set_expansion_cells(self, mode):
+        """raysh_set_expansion_cells: star cells of the expansion mode's block
+        pass ("auto", "always" or "never")."""
+        check(load().raysh_set_expansion_cells(self.handle, CELL_MODES[mode]))
 
     def set_star_split(self, parts):
         """raysh_set_star_split: 1 = one pass, 0 = automatic, n = n parts."""

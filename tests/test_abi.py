@@ -154,6 +154,7 @@ def test_other_argument_errors(lib):
     assert lib.raysh_set_star_split(None, 2) == R.EINVAL
     assert lib.raysh_set_expansion(None, 0.25) == R.EINVAL
     assert lib.raysh_set_expansion_block(None, 1) == R.EINVAL
+    assert lib.raysh_set_expansion_cells(None, 0) == R.EINVAL
     assert lib.raysh_expansion_order() >= 16
     assert lib.raysh_list_tiles(2, None, 0) == -R.EINVAL
     assert lib.raysh_free(None) == R.OK

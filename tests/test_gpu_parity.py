@@ -492,12 +492,14 @@ def test_expansion_matches_oracle_small(torch, small, small_oracle, block):
     bx, by, b, counts, n, s = small_oracle
     with R.Context(small.lens) as ctx:
         ctx.set_expansion_block(block)
-        for theta in (0.3, 0.25, 0.1):
-            ctx.set_expansion(theta)
-            gx, gy, gb = ctx.shoot(small.rays, "fp64_expansion", small.pix)
-            assert np.all(np.abs(_np(gx) - bx) <= BETA_TOL * s), theta
-            assert np.all(np.abs(_np(gy) - by) <= BETA_TOL * s), theta
-            assert np.count_nonzero(_np(gb) != b) <= MISBIN_FP64 * b.size
+        for cells in ("never", "always"):
+            ctx.set_expansion_cells(cells)
+            for theta in (0.3, 0.25, 0.1):
+                ctx.set_expansion(theta)
+                gx, gy, gb = ctx.shoot(small.rays, "fp64_expansion", small.pix)
+                assert np.all(np.abs(_np(gx) - bx) <= BETA_TOL * s), (cells, theta)
+                assert np.all(np.abs(_np(gy) - by) <= BETA_TOL * s), (cells, theta)
+                assert np.count_nonzero(_np(gb) != b) <= MISBIN_FP64 * b.size
         m, nb = ctx.map(small.rays, small.pix, "fp64_expansion", n_binned=True)
         assert 0.5 * (np.abs(_np(m) - counts).sum() + abs(nb - n)) <= MISBIN_FP64 * b.size
         with pytest.raises(R.RayshError):
@@ -506,6 +508,8 @@ def test_expansion_matches_oracle_small(torch, small, small_oracle, block):
             ctx.set_expansion(0.5)
         with pytest.raises(R.RayshError):
             ctx.set_expansion_block(3)
+        with pytest.raises(R.RayshError):
+            R.check(R.load().raysh_set_expansion_cells(ctx.handle, 3))
         with pytest.raises(R.RayshError):
             ctx.set_tile("fp64_expansion", 4, 4)
         with pytest.raises(R.RayshError):
@@ -568,8 +572,9 @@ def test_expansion_precision_study_full_lattice(torch):
         assert frac <= MISBIN_FP64
 
 
+@pytest.mark.parametrize("cells", ["never", "always"])
 @pytest.mark.parametrize("block", [1, 2, 4])
-def test_expansion_dense_cluster_falls_back(torch, block):
+def test_expansion_dense_cluster_falls_back(torch, block, cells):
     """More near stars than the lists hold (3000 stars within 0.3 of the
     lattice centre): those blocks sum every star directly; the result still
     matches the oracle ray by ray.  With a cluster off to one side, other
@@ -590,6 +595,7 @@ def test_expansion_dense_cluster_falls_back(torch, block):
         s = ora.error_scale_block(lens, rays)
         with R.Context(lens) as ctx:
             ctx.set_expansion_block(block)
+            ctx.set_expansion_cells(cells)
             gx, gy, gb = ctx.shoot(rays, "fp64_expansion", pix)
             assert np.all(np.abs(_np(gx) - ox) <= BETA_TOL * s), shift
             assert np.all(np.abs(_np(gy) - oy) <= BETA_TOL * s), shift
@@ -616,22 +622,27 @@ def test_star_upload_chunk_boundaries(torch, n_stars):
         assert np.count_nonzero(_np(gb) != ob) == 0
 
 
+@pytest.mark.parametrize("cells", ["never", "always"])
 @pytest.mark.parametrize("block", [1, 4])
-def test_expansion_degenerate_star_fields(torch, block):
-    """No stars, one star, massless stars, and a star exactly on a ray (that
-    ray is dropped, as in the oracle), in the expansion mode."""
+def test_expansion_degenerate_star_fields(torch, block, cells):
+    """No stars, one star, massless stars, a star exactly on a ray (that ray
+    is dropped, as in the oracle), stars on a line (a grid of one cell row)
+    and stars all at one point (no grid), in the expansion mode."""
     rays = (-1.5, -1.25, 3 / 160, 2.5 / 130, 160, 130, 0, 0)
     pix = (-2.0, -2.0, 4 / 64, 4 / 64, 64, 64)
     tx0 = -1.5 + (37 + 0.5) * (3 / 160)   # the image angle of ray (37, 51)
     ty0 = -1.25 + (51 + 0.5) * (2.5 / 130)
+    line = np.linspace(-40.0, 40.0, 400)
     cases = [([], [], []), ([0.3], [-0.2], [1.0]), ([0.3, -0.4, 0.9], [-0.2, 0.5, 0.1], [0.0, 0.0, 0.0]),
-             ([tx0, 0.7], [ty0, -0.6], [0.5, 0.8])]
+             ([tx0, 0.7], [ty0, -0.6], [0.5, 0.8]), (line, np.full(400, 0.37), np.full(400, 0.01)),
+             (np.full(50, 3.5), np.full(50, -2.5), np.full(50, 0.02))]
     for xs, ys, ms in cases:
         lens = (0.1, 0.2, -0.05, np.array(xs, float), np.array(ys, float), np.array(ms, float))
         ox, oy, ob = ora.shoot(lens, rays, pix)
         s = ora.error_scale_block(lens, rays)
         with R.Context(lens) as ctx:
             ctx.set_expansion_block(block)
+            ctx.set_expansion_cells(cells)
             gx, gy, gb = ctx.shoot(rays, "fp64_expansion", pix)
             gx, gy, gb = _np(gx), _np(gy), _np(gb)
             fin = np.isfinite(ox) & np.isfinite(oy)
@@ -639,6 +650,35 @@ def test_expansion_degenerate_star_fields(torch, block):
             assert np.all(np.abs(gx[fin] - ox[fin]) <= BETA_TOL * s[fin])
             assert np.all(np.abs(gy[fin] - oy[fin]) <= BETA_TOL * s[fin])
             assert np.count_nonzero(gb != ob) == 0
+
+
+@pytest.mark.parametrize("block", [1, 2, 4])
+def test_expansion_star_cells_wide_field(torch, block):
+    """20000 stars over a disk of radius 200 around a small lattice: most
+    star cells lie far from every block and enter through their multipole
+    expansions.  Per ray the result holds the FP64 bar against the oracle,
+    with cells and without, and the two agree in every bin."""
+    rng = np.random.default_rng(170)
+    n = 20000
+    r = 200.0 * np.sqrt(rng.random(n))
+    phi = 2 * np.pi * rng.random(n)
+    lens = (0.0, 0.1, 0.05, r * np.cos(phi), r * np.sin(phi), rng.uniform(0.05, 0.15, n))
+    rays = (-3.0, -3.0, 6 / 256, 6 / 256, 256, 256, 0, 0)
+    pix = (-2.5, -2.5, 5 / 64, 5 / 64, 64, 64)
+    _say("oracle: 256^2 rays x 20000 stars")
+    ox, oy, ob = ora.shoot(lens, rays, pix)
+    s = ora.error_scale_block(lens, rays)
+    bins = {}
+    with R.Context(lens) as ctx:
+        ctx.set_expansion_block(block)
+        for cells in ("always", "never"):
+            ctx.set_expansion_cells(cells)
+            gx, gy, gb = ctx.shoot(rays, "fp64_expansion", pix)
+            gx, gy, bins[cells] = _np(gx), _np(gy), _np(gb)
+            assert np.all(np.abs(gx - ox) <= BETA_TOL * s), cells
+            assert np.all(np.abs(gy - oy) <= BETA_TOL * s), cells
+            assert np.count_nonzero(bins[cells] != ob) <= 1, cells
+    assert np.array_equal(bins["always"], bins["never"])
 
 
 def _oracle_threaded(lens, rays, pix, threads):
