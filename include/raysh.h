@@ -155,8 +155,8 @@ int raysh_set_expansion(raysh_ctx *ctx, double theta_open);
  * once, then re-tests only that block's near stars for each tile (block 1:
  * one tile, one test).  0 (the default) picks the block by a cost model:
  * a workgroup costs about n_stars + 16384 block^2 star-equivalents, and
- * workgroups run in rounds of three per compute unit (two from 65536
- * stars on), a part-filled round counted in proportion.  The block
+ * workgroups run in rounds of three per compute unit, a part-filled round
+ * counted in proportion.  The block
  * changes the order of floating-point operations, not the accuracy bound.
  * EINVAL for a NULL context or a block other than 0, 1, 2 or 4. */
 int raysh_set_expansion_block(raysh_ctx *ctx, int block);
@@ -175,8 +175,8 @@ int raysh_set_expansion_block(raysh_ctx *ctx, int block);
  * cells; their direct sums then go in cell order (index order within a
  * cell) instead of index order.
  *   RAYSH_CELLS_AUTO (default): cells from 65536 stars on (below that the
- *     block pass is a small share of the time, and the translations' registers
- *     would cost the kernel a third workgroup per compute unit).
+ *     block pass is a small share of the time, and the build, a round trip
+ *     through the host per context, would not pay back within a few maps).
  *   RAYSH_CELLS_ALWAYS: cells whenever the stars span a nonzero box.
  *   RAYSH_CELLS_NEVER: the block pass expands every far star on its own.
  * The grid has at most 4096 cells and 256 rows and columns; building it

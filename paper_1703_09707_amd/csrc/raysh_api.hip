@@ -84,10 +84,24 @@ int launch(raysh_ctx *c, const ShootParams &p, int precision, const char *what) 
             }
             cells = c->cells.view;
         }
-        e = raysh::launch_shoot_expansion(
-            p, cells, c->theta_open,
-            c->expansion_block ? c->expansion_block : raysh::expansion_block(p.nx, p.ny, c->n_stars, c->n_cu),
-            c->stream);
+        const int block =
+            c->expansion_block ? c->expansion_block : raysh::expansion_block(p.nx, p.ny, c->n_stars, c->n_cu);
+        const size_t need = raysh::expansion_workspace_bytes(p.nx, p.ny, block);
+        if (need > c->far_bytes) {
+            e = hipStreamSynchronize(c->stream);   // the old workspace may still be read
+            if (e != hipSuccess) return hip_error(e, what);
+            if (c->d_far) (void)hipFree(c->d_far);
+            c->d_far = nullptr;
+            c->far_bytes = 0;
+            e = hipMalloc(&c->d_far, need);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                c->d_far = nullptr;
+                return set_error(RAYSH_ENOMEM, "%s: expansion workspace of %zu bytes", what, need);
+            }
+            c->far_bytes = need;
+        }
+        e = raysh::launch_shoot_expansion(p, cells, c->theta_open, block, c->d_far, c->stream);
     }
     if (e != hipSuccess) return hip_error(e, what);
     return RAYSH_OK;
@@ -478,6 +492,7 @@ int raysh_free(raysh_ctx *ctx) {
         if (ctx->d_stars) (void)hipFree(ctx->d_stars);
         if (ctx->d_counter) (void)hipFree(ctx->d_counter);
         if (ctx->d_partial) (void)hipFree(ctx->d_partial);
+        if (ctx->d_far) (void)hipFree(ctx->d_far);
         if (ctx->h_counter) (void)hipHostFree(ctx->h_counter);
         raysh::free_star_cells(ctx->cells);
     }

@@ -23,6 +23,8 @@ struct raysh_ctx {
     raysh::StarCellStore cells;            // built on the first call that uses them
     double2 *d_partial = nullptr;          // split-K workspace
     size_t partial_bytes = 0;
+    void *d_far = nullptr;                 // expansion mode: the blocks' coefficients and near lists
+    size_t far_bytes = 0;
     int n_cu = 0;
 };
 

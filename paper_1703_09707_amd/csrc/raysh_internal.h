@@ -115,7 +115,10 @@ void free_star_cells(StarCellStore &cells);
 // cells (cells.ncx > 0) the block pass takes distant cells through their
 // multipole expansions.
 hipError_t launch_shoot_expansion(const ShootParams &p, const StarCells &cells, double theta_open, int block,
-                                  hipStream_t s);
+                                  void *workspace, hipStream_t s);
+// Device workspace launch_shoot_expansion needs for an nx x ny lattice block
+// (each workgroup block's coefficients and near-star lists, about 8.6 KB each).
+size_t expansion_workspace_bytes(int64_t nx, int64_t ny, int block);
 int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu);
 int expansion_order();
 

@@ -46,7 +46,6 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kNearPerWave = 512;     // near-star list capacity of each wave
 constexpr int kCX = 4, kCY = 4;       // rays per lane
 constexpr int kTile = kLanesX * kCX;  // 64 rays per tile side
-constexpr int kManyStars = 65536;     // from here on, two workgroups per compute unit
 static_assert(kLanesX * kCX == kLanesY * kCY, "square tiles");
 
 constexpr int kMaxTiles = 16;         // tiles per workgroup block, at most 4 x 4
@@ -67,6 +66,15 @@ struct ExpShared {
     int row_first[kCellMaxRows];                      // first record of the band's stars
     int row_pref[kCellMaxRows];                       // the bands' stars before this row
     int wave_tot[kWaves];
+};
+
+// What a block's pass over the stars leaves for its tiles: the block's
+// coefficients and its near stars, each wave's list in order (the counts
+// include stars beyond the lists' capacity).
+struct BlockFar {
+    double2 A[kOrder + 1];
+    int outer_n[kWaves];
+    int outer_idx[kWaves][kNearPerWave];
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -381,13 +389,57 @@ __device__ __forceinline__ void block_pass_cells(const StarCells &cells, double 
         bcx, bcy, brho, r_near2, acc, ex.outer_idx, ex.outer_n);
 }
 
-// WPS waves per SIMD (workgroups per compute unit): 3 suits few stars per
-// block, where the tiles' work dominates and more workgroups hide its
-// barriers; 2 suits many, where the pass over the stars dominates and
-// needs its registers (at 3 it spills a few values inside that loop).
-template <int L, int WPS, bool CELLS>
-__global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootParams p, StarCells cells,
-                                                                       double theta_open, int blocks_x) {
+// The block pass, one workgroup per block of block_rays x block_rays rays:
+// the stars far from the block enter its local expansion A (through star
+// cells when CELLS), the near ones go to its lists; both are written to
+// far[blockIdx.x] for the tile kernel.  Two workgroups per compute unit: the
+// cells' translations need the registers.
+template <bool CELLS>
+__global__ __launch_bounds__(kThreads, 2) void expansion_block_kernel(ShootParams p, StarCells cells,
+                                                                      double theta_open, int blocks_x,
+                                                                      int block_rays, BlockFar *__restrict__ far) {
+    __shared__ ExpShared ex;
+    const int64_t b_i = (int64_t)(blockIdx.x % blocks_x) * block_rays;
+    const int64_t b_j = (int64_t)(blockIdx.x / blocks_x) * block_rays;
+    const ConstStar *st = const_stars(uniform_ptr(p.stars));
+    const int n = uniform(p.n_stars);
+    const double inv_theta = uniform_f64(1.0 / theta_open);
+    double bcx, bcy, brho;
+    region_uniform(p, b_i, b_j, block_rays, bcx, bcy, brho);
+    double2 acc[kOrder + 1];
+#pragma unroll
+    for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
+    const double r_near = brho * inv_theta;
+    const double r_near2 = uniform_f64(r_near * r_near);
+    if constexpr (CELLS) {
+        block_pass_cells(cells, bcx, bcy, brho, inv_theta, r_near2, acc, ex);
+    } else {
+        p2l_pass(
+            n,
+            [&](int e, int &k, double &x, double &y, double &m) {
+                k = e;
+                x = st[e].x;
+                y = st[e].y;
+                m = st[e].m;
+            },
+            bcx, bcy, brho, r_near2, acc, ex.outer_idx, ex.outer_n);
+    }
+    reduce_coeffs<false>(acc, ex, ex.A);   // its barriers also publish outer_n
+    BlockFar *f = far + blockIdx.x;
+    if (threadIdx.x <= kOrder) f->A[threadIdx.x] = ex.A[threadIdx.x];
+    if (threadIdx.x < kWaves) f->outer_n[threadIdx.x] = ex.outer_n[threadIdx.x];
+    for (int w = 0; w < kWaves; ++w) {
+        const int cnt = min(ex.outer_n[w], kNearPerWave);
+        for (int i = threadIdx.x; i < cnt; i += kThreads) f->outer_idx[w][i] = ex.outer_idx[w][i];
+    }
+}
+
+// The tiles of a block of L x L tiles, after its block pass.  WPS waves per
+// SIMD (workgroups per compute unit).
+template <int L, int WPS>
+__global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootParams p, double theta_open,
+                                                                       int blocks_x,
+                                                                       const BlockFar *__restrict__ far) {
     __shared__ BinShared sh;
     __shared__ ExpShared ex;
     bin_shared_init(sh);
@@ -400,29 +452,18 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
     const int n = uniform(p.n_stars);
     const double inv_theta = uniform_f64(1.0 / theta_open);
 
-    // --- the block: far stars into A, near stars into the outer lists
+    // --- the block: its coefficients A and near stars, from the block pass
     double bcx, bcy, brho;
     region_uniform(p, b_i, b_j, kTile * L, bcx, bcy, brho);
     {
-        double2 acc[kOrder + 1];
-#pragma unroll
-        for (int q = 0; q <= kOrder; ++q) acc[q] = make_double2(0.0, 0.0);
-        const double r_near = brho * inv_theta;
-        const double r_near2 = uniform_f64(r_near * r_near);
-        if constexpr (CELLS) {
-            block_pass_cells(cells, bcx, bcy, brho, inv_theta, r_near2, acc, ex);
-        } else {
-            p2l_pass(
-                n,
-                [&](int e, int &k, double &x, double &y, double &m) {
-                    k = e;
-                    x = st[e].x;
-                    y = st[e].y;
-                    m = st[e].m;
-                },
-                bcx, bcy, brho, r_near2, acc, ex.outer_idx, ex.outer_n);
+        const BlockFar *f = far + blockIdx.x;
+        if (threadIdx.x <= kOrder) ex.A[threadIdx.x] = f->A[threadIdx.x];
+        if (threadIdx.x < kWaves) ex.outer_n[threadIdx.x] = f->outer_n[threadIdx.x];
+        for (int w = 0; w < kWaves; ++w) {
+            const int cnt = min(uniform(f->outer_n[w]), kNearPerWave);
+            for (int i = threadIdx.x; i < cnt; i += kThreads) ex.outer_idx[w][i] = f->outer_idx[w][i];
         }
-        reduce_coeffs<false>(acc, ex, ex.A);   // its barriers also publish outer_n
+        __syncthreads();
     }
     bool overflow = false;
     int n_outer = 0;
@@ -545,23 +586,21 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
     }
 }
 
-// Without cells: three workgroups per compute unit below kManyStars stars,
-// two from there on.  With cells the translations need the registers of
-// two (at three they would spill about 100 VGPRs).
+// The block pass (with or without cells), then the tiles at three
+// workgroups per compute unit (measured faster than two at every star count
+// once the block pass is a kernel of its own).
 template <int L>
 hipError_t launch_level(const ShootParams &p, const StarCells &cells, double theta_open, int64_t tiles_x,
-                        int64_t tiles_y, hipStream_t s) {
+                        int64_t tiles_y, BlockFar *far, hipStream_t s) {
     const int64_t bx = (tiles_x + L - 1) / L, by = (tiles_y + L - 1) / L;
     const dim3 grid((unsigned)(bx * by));
     if (cells.ncx > 0)
-        hipLaunchKernelGGL((expansion_fp64_kernel<L, 2, true>), grid, dim3(kThreads), 0, s, p, cells, theta_open,
-                           (int)bx);
-    else if (p.n_stars < kManyStars)
-        hipLaunchKernelGGL((expansion_fp64_kernel<L, 3, false>), grid, dim3(kThreads), 0, s, p, cells, theta_open,
-                           (int)bx);
+        hipLaunchKernelGGL(expansion_block_kernel<true>, grid, dim3(kThreads), 0, s, p, cells, theta_open, (int)bx,
+                           kTile * L, far);
     else
-        hipLaunchKernelGGL((expansion_fp64_kernel<L, 2, false>), grid, dim3(kThreads), 0, s, p, cells, theta_open,
-                           (int)bx);
+        hipLaunchKernelGGL(expansion_block_kernel<false>, grid, dim3(kThreads), 0, s, p, cells, theta_open, (int)bx,
+                           kTile * L, far);
+    hipLaunchKernelGGL((expansion_fp64_kernel<L, 3>), grid, dim3(kThreads), 0, s, p, theta_open, (int)bx, far);
     return hipGetLastError();
 }
 
@@ -601,11 +640,11 @@ int expansion_order() { return kOrder; }
 // The block that minimises a simple cost model: a workgroup costs about
 // N* + 16384 L^2 star-equivalents (its pass over all stars, then L^2 tiles
 // of Horner steps, near stars and binning, measured on MI355X), and the
-// workgroups run in rounds of three (two from kManyStars stars on) per
-// compute unit, a part-filled round counted in proportion.
+// workgroups run in rounds of three per compute unit, a part-filled round
+// counted in proportion.
 int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu) {
     const int64_t tx = (nx + kTile - 1) / kTile, ty = (ny + kTile - 1) / kTile;
-    const int64_t slots = (n_stars < kManyStars ? 3 : 2) * (int64_t)(n_cu > 0 ? n_cu : 256);
+    const int64_t slots = 3 * (int64_t)(n_cu > 0 ? n_cu : 256);
     int best = 1;
     double best_cost = 0.0;
     for (int L : {1, 2, 4}) {
@@ -620,16 +659,23 @@ int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu) {
     return best;
 }
 
+size_t expansion_workspace_bytes(int64_t nx, int64_t ny, int block) {
+    const int64_t tiles_x = (nx + kTile - 1) / kTile, tiles_y = (ny + kTile - 1) / kTile;
+    const int64_t blocks = ((tiles_x + block - 1) / block) * ((tiles_y + block - 1) / block);
+    return (size_t)blocks * sizeof(BlockFar);
+}
+
 hipError_t launch_shoot_expansion(const ShootParams &p, const StarCells &cells, double theta_open, int block,
-                                  hipStream_t s) {
+                                  void *workspace, hipStream_t s) {
     ShootParams q = p;
     const int64_t tiles_x = (p.nx + kTile - 1) / kTile;
     const int64_t tiles_y = (p.ny + kTile - 1) / kTile;
     q.tiles_x = (int32_t)tiles_x;
+    BlockFar *far = static_cast<BlockFar *>(workspace);
     switch (block) {
-        case 1: return launch_level<1>(q, cells, theta_open, tiles_x, tiles_y, s);
-        case 2: return launch_level<2>(q, cells, theta_open, tiles_x, tiles_y, s);
-        case 4: return launch_level<4>(q, cells, theta_open, tiles_x, tiles_y, s);
+        case 1: return launch_level<1>(q, cells, theta_open, tiles_x, tiles_y, far, s);
+        case 2: return launch_level<2>(q, cells, theta_open, tiles_x, tiles_y, far, s);
+        case 4: return launch_level<4>(q, cells, theta_open, tiles_x, tiles_y, far, s);
         default: return hipErrorInvalidValue;
     }
 }
