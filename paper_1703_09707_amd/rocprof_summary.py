@@ -26,6 +26,7 @@ KERNEL_SOURCES = {
     "partial_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "finish_fp64_kernel": ["csrc/shoot_fp64.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "expansion_fp64_kernel": ["csrc/shoot_expansion.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
+    "expansion_block_kernel": ["csrc/shoot_expansion.hip", "csrc/ray_common.h", "csrc/raysh_internal.h"],
     "light_curve_kernel": ["csrc/light_curves.hip", "csrc/smooth.h"],
     "light_curve_track_kernel": ["csrc/light_curves.hip", "csrc/smooth.h"],
 }
