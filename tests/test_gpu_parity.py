@@ -516,6 +516,29 @@ def test_expansion_matches_oracle_small(torch, small, small_oracle, block):
             R.map_batch([ctx], [small.rays], [small.pix], "fp64_expansion")
 
 
+def test_expansion_workspace_grows_in_one_context(torch, small, small_oracle):
+    """One context maps lattice blocks of growing size, and changes its
+    workgroup block, in the expansion mode: the workspace of the blocks'
+    coefficients and near lists is reallocated as needed, and every call
+    still matches the oracle ray by ray."""
+    bx, by, b, _, _, s = small_oracle
+    nx_all = small.rays.nx
+    with R.Context(small.lens) as ctx:
+        for block, (nx, ny) in ((1, (64, 64)), (1, (300, 200)), (4, (300, 200)), (1, (1000, 1000)),
+                                (2, (130, 70))):
+            ctx.set_expansion_block(block)
+            sub = small.rays.block(0, 0, nx, ny)
+            gx, gy, gb = ctx.shoot(sub, "fp64_expansion", small.pix)
+            sel = (slice(0, ny), slice(0, nx))
+            want_x = bx.reshape(-1, nx_all)[sel].ravel()
+            want_y = by.reshape(-1, nx_all)[sel].ravel()
+            want_b = b.reshape(-1, nx_all)[sel].ravel()
+            scale = s.reshape(-1, nx_all)[sel].ravel()
+            assert np.all(np.abs(_np(gx).ravel() - want_x) <= BETA_TOL * scale), (block, nx, ny)
+            assert np.all(np.abs(_np(gy).ravel() - want_y) <= BETA_TOL * scale), (block, nx, ny)
+            assert np.count_nonzero(_np(gb).ravel() != want_b) <= 1, (block, nx, ny)
+
+
 @pytest.mark.parametrize("block", [2, 4])
 @pytest.mark.parametrize("i0,j0,nx,ny", [(0, 0, 300, 200), (37, 501, 130, 499), (999, 0, 1, 1000),
                                          (5, 5, 64, 64), (0, 0, 0, 10)])
