@@ -31,6 +31,19 @@
 // With L = 1 the block is the tile and the second test is skipped.  If a
 // block has more near stars than its lists hold, its tiles sum every star
 // directly.
+//
+// The block pass is a kernel of its own (expansion_block_kernel), which
+// leaves each block's polynomial and near lists in a workspace for the
+// tile kernel (expansion_fp64_kernel); each runs at the occupancy its own
+// registers allow.
+//
+// Star cells.  Optionally the stars are sorted once by the cell of a
+// regular grid, and each cell gets a multipole expansion of its stars
+// (M_j = sum_k m_k ((z_k - z_c) / r_c)^j).  The block pass then takes every
+// cell far enough from the block, (r_c + rho) / theta_open or more between
+// centres, through one multipole-to-local translation, and tests only the
+// stars of the other cells one by one: the cell expansion of distant stars
+// that tree codes rest on, at the same truncation bound per cell.
 #include <algorithm>
 #include <cmath>
 #include <vector>
