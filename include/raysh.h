@@ -31,7 +31,11 @@
  * every other pointer (maps, per-ray outputs) is caller-owned DEVICE memory
  * on the context's device.  The library never allocates caller outputs.
  * Work is enqueued on the context's HIP stream and is asynchronous unless a
- * function says otherwise.
+ * function says otherwise.  Context-owned work buffers (the split-K partial
+ * sums, the expansion mode's per-block records, its star cells) are
+ * allocated on first use and grown when a larger call needs them; such a
+ * call first synchronizes the context's stream, and the first call that
+ * uses star cells also copies the stars to the host to build them.
  *
  * Errors: every function returns RAYSH_OK (0) or a RAYSH_E* code, and
  * raysh_last_error() gives a message for the calling thread's last error.
