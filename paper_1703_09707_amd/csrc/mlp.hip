@@ -9,10 +9,13 @@
 // against shooter histograms.  Parameter layout (FP32, flat):
 // W1[n_in][h], b1[h], W2[h][h], b2[h], W3[h][n_out], b3[n_out].
 //
-// One LDS-tiled FP32 GEMM serves every product of the forward and backward
-// passes; it computes C[M][N] = sum_k A(m, k) B(k, n) with A and B read
-// directly or transposed, B in FP32 or BF16, and a fused epilogue.  All
-// reductions run in a fixed order, so results are deterministic.
+// One LDS-tiled FP32 GEMM on the matrix cores serves every product of the
+// forward and backward passes; it computes C[M][N] = sum_k A(m, k) B(k, n)
+// with A and B read directly or transposed, B in FP32 or BF16 (widened to
+// FP32 exactly), and a fused epilogue.  The products are FP32 MFMAs
+// (v_mfma_f32_16x16x4f32: FP32 operands and accumulation, so activations
+// stay FP32).  All reductions run in a fixed order, so results are
+// deterministic.
 #include <cmath>
 #include <limits>
 #include <vector>
@@ -54,9 +57,15 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(const float *__restr
                                                             float *__restrict__ C2) {
     __shared__ float As[BK][BM + 4];
     __shared__ float Bs[BK][BN + 4];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;   // the wave's quarter of the tile
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    float acc[4][4] = {};
+    typedef float floatx4 __attribute__((ext_vector_type(4)));
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj) acc[si][sj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = 0; k0 < K; k0 += BK) {
         // stage A tile: BM x BK elements, 4 per thread
         for (int e = threadIdx.x; e < BM * BK; e += kGemmThreads) {
@@ -80,36 +89,43 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(const float *__restr
             Bs[kk][nn] = v;
         }
         __syncthreads();
+        // each wave: a 32 x 32 quarter of the tile as 2 x 2 MFMA tiles of
+        // 16 x 16, four steps of k = 4 per staged chunk.  Operands of
+        // v_mfma_f32_16x16x4f32: lane l gives A(row l % 16, k l / 16) and
+        // B(k l / 16, column l % 16).
 #pragma unroll
-        for (int kk = 0; kk < BK; ++kk) {
-            float a[4], b[4];
+        for (int kq = 0; kq < BK; kq += 4) {
+            const int kk = kq + lane / 16;
+            float a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+            for (int si = 0; si < 2; ++si) a[si] = As[kk][wm + si * 16 + lane % 16];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+            for (int sj = 0; sj < 2; ++sj) b[sj] = Bs[kk][wn + sj * 16 + lane % 16];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int si = 0; si < 2; ++si)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+                for (int sj = 0; sj < 2; ++sj)
+                    acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[si], b[sj], acc[si][sj], 0, 0, 0);
         }
         __syncthreads();
     }
+    // lane l holds rows 4 (l / 16) + r, column l % 16 of each 16 x 16 tile
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + ty * 4 + i;
-        if (m >= M) continue;
+    for (int si = 0; si < 2; ++si)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = n0 + tx * 4 + j;
-            if (n >= N) continue;
-            const int64_t o = (int64_t)m * ldc + n;
-            float v = acc[i][j];
-            if (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) v += bias[n];
-            if (EPI == EPI_GELU_GRAD) v *= gelu_grad(aux[o]);
-            C[o] = v;
-            if (EPI == EPI_BIAS_GELU) C2[o] = gelu(v);
-        }
-    }
+        for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + si * 16 + 4 * (lane / 16) + r;
+                const int n = n0 + wn + sj * 16 + lane % 16;
+                if (m >= M || n >= N) continue;
+                const int64_t o = (int64_t)m * ldc + n;
+                float v = acc[si][sj][r];
+                if (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) v += bias[n];
+                if (EPI == EPI_GELU_GRAD) v *= gelu_grad(aux[o]);
+                C[o] = v;
+                if (EPI == EPI_BIAS_GELU) C2[o] = gelu(v);
+            }
 }
 
 template <bool A_T, bool B_T, bool B_BF16, int EPI>
