@@ -4,12 +4,21 @@
  * A plain, slow, single-threaded FP64 implementation of backward ray
  * shooting through a random star field, written from Chen, Kantowski, Dai,
  * Baron & Van der Mark (2017), "Accelerating gravitational microlensing
- * simulations using the Xeon Phi coprocessor" (arXiv:1703.09707):
- *   - the lens equation, Sec. 1, Eq. (1)-(3): beta = theta - alpha, with
- *     alpha = K theta + sum_k m_k (theta - theta_k) / |theta - theta_k|^2 and
- *     K = [[kappa_c + gamma_1, gamma_2], [gamma_2, kappa_c - gamma_1]];
- *   - the per-ray steps of Algorithm 1 (Sec. 2.2), in its order: image
- *     angle, macro term, star sum in index order, source angle, pixel, count.
+ * simulations using the Xeon Phi coprocessor" (arXiv:1703.09707).
+ *
+ * What is computed is a composition of two maps, applied to every ray of a
+ * regular image-plane lattice:
+ *   - the lens map theta -> beta of Sec. 1, Eq. (2)-(3):
+ *       beta = theta - alpha(theta),
+ *       alpha(theta) = K theta + sum_k m_k (theta - theta_k) / |theta - theta_k|^2,
+ *       K = [[kappa_c + gamma_1, gamma_2], [gamma_2, kappa_c - gamma_1]];
+ *   - the pixel function beta -> (i_s, j_s) of the source-plane window,
+ *     undefined (the ray is not counted) outside the window.
+ * The magnification map of Algorithm 1 (Sec. 2.2) is the histogram of the
+ * pixel function over the lattice's rays: mag[j_s][i_s] is the number of
+ * rays whose source position falls in pixel (i_s, j_s).  Within alpha the
+ * smooth term comes first and the stars follow in index order, each
+ * operation one IEEE-rounded step.
  *
  * Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark may load this library.  It shares no code, header or constant
@@ -23,11 +32,24 @@
  *     the pixel coordinate is (beta - X0) / Px with IEEE division, the window
  *     test is done in FP64 before the integer conversion, and the map is
  *     row-major with row js (the paper's mag[j_s, i_s]);
- *   - a ray whose beta is not finite (it hit a star exactly) is dropped.
+ *   - a ray whose beta is not finite (it hit a star exactly) is not counted.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+
+/* The lens of Eq. (1): smooth convergence, shear and the point masses. */
+typedef struct {
+    double kappa_c, gamma1, gamma2;
+    int64_t n_stars;
+    const double *xs, *ys, *ms;
+} lens_t;
+
+/* The source-plane window and its pixels. */
+typedef struct {
+    double X0, Y0, Px, Py;
+    int64_t NX, NY;
+} window_t;
 
 /* Image angle of lattice index idx (cell-centred). */
 static double image_angle(double origin, int64_t idx, double step)
@@ -37,48 +59,56 @@ static double image_angle(double origin, int64_t idx, double step)
     return origin + t;
 }
 
-/* Eq. (3) then Eq. (2) for one ray: returns beta = theta - alpha. */
-static void lens_one_ray(double kappa_c, double gamma1, double gamma2,
-                         int64_t n_stars, const double *xs, const double *ys,
-                         const double *ms, double tx, double ty,
-                         double *bx, double *by)
+/* The lens map, Eq. (2)-(3): beta = theta - alpha(theta). */
+static void lens_map(const lens_t *L, double tx, double ty, double *bx, double *by)
 {
-    /* first term of Eq. (3): the smooth matter and shear */
-    double ax = (kappa_c + gamma1) * tx + gamma2 * ty;
-    double ay = gamma2 * tx + (kappa_c - gamma1) * ty;
-    /* second term of Eq. (3): the stars, in index order */
-    for (int64_t k = 0; k < n_stars; ++k) {
-        double ex = tx - xs[k];
-        double ey = ty - ys[k];
+    /* smooth matter and shear: K theta */
+    double ax = (L->kappa_c + L->gamma1) * tx + L->gamma2 * ty;
+    double ay = L->gamma2 * tx + (L->kappa_c - L->gamma1) * ty;
+    /* the point masses, in index order */
+    for (int64_t k = 0; k < L->n_stars; ++k) {
+        double ex = tx - L->xs[k];
+        double ey = ty - L->ys[k];
         double r2 = ex * ex + ey * ey;
-        double w = ms[k] / r2;
+        double w = L->ms[k] / r2;
         ax += w * ex;
         ay += w * ey;
     }
-    /* Eq. (2) */
     *bx = tx - ax;
     *by = ty - ay;
 }
 
-/* Linear pixel index js*NX + is of a source angle, or -1 when the ray is
- * dropped (non-finite) or lands outside the source window. */
-static int64_t pixel_index(double bx, double by, double X0, double Y0,
-                           double Px, double Py, int64_t NX, int64_t NY)
+/* The pixel function: linear index js*NX + is of the pixel holding beta, or
+ * -1 when beta is not finite or lies outside the window. */
+static int64_t pixel_of(const window_t *W, double bx, double by)
 {
     if (!isfinite(bx) || !isfinite(by))
         return -1;
-    double u = (bx - X0) / Px;
-    double v = (by - Y0) / Py;
-    if (!(u >= 0.0 && u < (double)NX && v >= 0.0 && v < (double)NY))
+    double u = (bx - W->X0) / W->Px;
+    double v = (by - W->Y0) / W->Py;
+    if (!(u >= 0.0 && u < (double)W->NX && v >= 0.0 && v < (double)W->NY))
         return -1;
     int64_t is = (int64_t)floor(u);
     int64_t js = (int64_t)floor(v);
-    return js * NX + is;
+    return js * W->NX + is;
+}
+
+static lens_t make_lens(double kappa_c, double gamma1, double gamma2, int64_t n_stars,
+                        const double *xs, const double *ys, const double *ms)
+{
+    lens_t L = {kappa_c, gamma1, gamma2, n_stars, xs, ys, ms};
+    return L;
+}
+
+static window_t make_window(double X0, double Y0, double Px, double Py, int64_t NX, int64_t NY)
+{
+    window_t W = {X0, Y0, Px, Py, NX, NY};
+    return W;
 }
 
 /*
- * Per-ray source angles and pixel indices for the nx-by-ny block of rays
- * whose global lattice indices start at (i0, j0).  Outputs are j-major
+ * The lens map and the pixel function at every ray of the nx-by-ny block of
+ * the lattice whose global indices start at (i0, j0).  Outputs are j-major
  * (index j*nx + i); any output pointer may be NULL.
  */
 void ora_shoot(double kappa_c, double gamma1, double gamma2,
@@ -88,23 +118,24 @@ void ora_shoot(double kappa_c, double gamma1, double gamma2,
                double X0, double Y0, double Px, double Py, int64_t NX, int64_t NY,
                double *beta_x, double *beta_y, int64_t *bin)
 {
+    const lens_t L = make_lens(kappa_c, gamma1, gamma2, n_stars, xs, ys, ms);
+    const window_t W = make_window(X0, Y0, Px, Py, NX, NY);
     for (int64_t j = 0; j < ny; ++j) {
-        double ty = image_angle(y0, j0 + j, dy);
         for (int64_t i = 0; i < nx; ++i) {
-            double tx = image_angle(x0, i0 + i, dx);
             double bx, by;
-            lens_one_ray(kappa_c, gamma1, gamma2, n_stars, xs, ys, ms, tx, ty, &bx, &by);
+            lens_map(&L, image_angle(x0, i0 + i, dx), image_angle(y0, j0 + j, dy), &bx, &by);
             int64_t o = j * nx + i;
             if (beta_x) beta_x[o] = bx;
             if (beta_y) beta_y[o] = by;
-            if (bin) bin[o] = pixel_index(bx, by, X0, Y0, Px, Py, NX, NY);
+            if (bin) bin[o] = pixel_of(&W, bx, by);
         }
     }
 }
 
 /*
- * Algorithm 1 proper: adds one count per ray to counts[js*NX + is] (the map
- * is accumulated, not cleared).  Returns the number of rays binned.
+ * The magnification map of the block: adds to counts[p] the number of rays
+ * whose pixel is p (the map is accumulated, not cleared).  Returns the
+ * number of rays counted.
  */
 int64_t ora_map(double kappa_c, double gamma1, double gamma2,
                 int64_t n_stars, const double *xs, const double *ys, const double *ms,
@@ -113,27 +144,27 @@ int64_t ora_map(double kappa_c, double gamma1, double gamma2,
                 double X0, double Y0, double Px, double Py, int64_t NX, int64_t NY,
                 int32_t *counts)
 {
-    int64_t binned = 0;
+    const lens_t L = make_lens(kappa_c, gamma1, gamma2, n_stars, xs, ys, ms);
+    const window_t W = make_window(X0, Y0, Px, Py, NX, NY);
+    int64_t counted = 0;
     for (int64_t j = 0; j < ny; ++j) {
-        double ty = image_angle(y0, j0 + j, dy);
         for (int64_t i = 0; i < nx; ++i) {
-            double tx = image_angle(x0, i0 + i, dx);
             double bx, by;
-            lens_one_ray(kappa_c, gamma1, gamma2, n_stars, xs, ys, ms, tx, ty, &bx, &by);
-            int64_t p = pixel_index(bx, by, X0, Y0, Px, Py, NX, NY);
+            lens_map(&L, image_angle(x0, i0 + i, dx), image_angle(y0, j0 + j, dy), &bx, &by);
+            int64_t p = pixel_of(&W, bx, by);
             if (p >= 0) {
                 counts[p] += 1;
-                ++binned;
+                ++counted;
             }
         }
     }
-    return binned;
+    return counted;
 }
 
 /*
- * Source angles of an arbitrary list of rays given by global lattice
- * indices (ii[r], jj[r]); used to check sampled rays of large grids one
- * by one.
+ * The lens map and the pixel function at an arbitrary list of rays given by
+ * global lattice indices (ii[r], jj[r]); used to check sampled rays of large
+ * lattices one by one.
  */
 void ora_shoot_list(double kappa_c, double gamma1, double gamma2,
                     int64_t n_stars, const double *xs, const double *ys, const double *ms,
@@ -142,20 +173,23 @@ void ora_shoot_list(double kappa_c, double gamma1, double gamma2,
                     double X0, double Y0, double Px, double Py, int64_t NX, int64_t NY,
                     double *beta_x, double *beta_y, int64_t *bin)
 {
+    const lens_t L = make_lens(kappa_c, gamma1, gamma2, n_stars, xs, ys, ms);
+    const window_t W = make_window(X0, Y0, Px, Py, NX, NY);
     for (int64_t r = 0; r < n; ++r) {
-        double tx = image_angle(x0, ii[r], dx);
-        double ty = image_angle(y0, jj[r], dy);
         double bx, by;
-        lens_one_ray(kappa_c, gamma1, gamma2, n_stars, xs, ys, ms, tx, ty, &bx, &by);
+        lens_map(&L, image_angle(x0, ii[r], dx), image_angle(y0, jj[r], dy), &bx, &by);
         if (beta_x) beta_x[r] = bx;
         if (beta_y) beta_y[r] = by;
-        if (bin) bin[r] = pixel_index(bx, by, X0, Y0, Px, Py, NX, NY);
+        if (bin) bin[r] = pixel_of(&W, bx, by);
     }
 }
 
 /*
- * The rounding-error scale S = |theta|_inf + |K theta|_inf + sum_k m_k / r_k
- * of one ray; per-ray tolerances on beta are stated relative to it.
+ * The scale of the rounding errors of beta at one ray:
+ *   S = |theta|_inf + |K theta|_inf + sum_k m_k / r_k,
+ * the largest magnitude any term of beta = theta - K theta - sum_k (...)
+ * can take (each star term has length m_k / r_k).  Per-ray tolerances on
+ * beta are stated relative to it; by the triangle inequality |beta|_inf <= S.
  */
 double ora_error_scale(double kappa_c, double gamma1, double gamma2,
                        int64_t n_stars, const double *xs, const double *ys, const double *ms,

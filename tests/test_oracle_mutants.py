@@ -14,25 +14,32 @@ import test_oracle_pins as pins
 
 MUTANTS = {
     "star term sign": ("ax += w * ex;", "ax -= w * ex;"),
-    "x/y swapped in star offset": ("double ey = ty - ys[k];\n        double r2",
-                                   "double ey = ty - xs[k];\n        double r2"),
-    "shear transposed on x": ("double ax = (kappa_c + gamma1) * tx", "double ax = (kappa_c - gamma1) * tx"),
-    "shear transposed on y": ("double ay = gamma2 * tx + (kappa_c - gamma1) * ty;",
-                              "double ay = gamma2 * tx + (kappa_c + gamma1) * ty;"),
-    "off-diagonal operand": ("+ gamma2 * ty;", "+ gamma2 * tx;"),
-    "smooth matter dropped": ("double ay = gamma2 * tx + (kappa_c - gamma1) * ty;",
-                              "double ay = gamma2 * tx + (0.0 - gamma1) * ty;"),
+    "x/y swapped in star offset": ("double ey = ty - L->ys[k];", "double ey = ty - L->xs[k];"),
+    "shear transposed on x": ("double ax = (L->kappa_c + L->gamma1) * tx",
+                              "double ax = (L->kappa_c - L->gamma1) * tx"),
+    "shear transposed on y": ("double ay = L->gamma2 * tx + (L->kappa_c - L->gamma1) * ty;",
+                              "double ay = L->gamma2 * tx + (L->kappa_c + L->gamma1) * ty;"),
+    "off-diagonal operand": ("+ L->gamma2 * ty;", "+ L->gamma2 * tx;"),
+    "smooth matter dropped": ("double ay = L->gamma2 * tx + (L->kappa_c - L->gamma1) * ty;",
+                              "double ay = L->gamma2 * tx + (0.0 - L->gamma1) * ty;"),
     "distance term": ("double r2 = ex * ex + ey * ey;", "double r2 = ex * ex + ex * ey;"),
-    "mass dropped": ("double w = ms[k] / r2;", "double w = 1.0 / r2;"),
+    "mass dropped": ("double w = L->ms[k] / r2;", "double w = 1.0 / r2;"),
     "Eq. 2 sign": ("*bx = tx - ax;", "*bx = tx + ax;"),
     "cell corner instead of centre": ("double t = (double)idx + 0.5;", "double t = (double)idx;"),
-    "closed window": ("u >= 0.0 && u < (double)NX", "u >= 0.0 && u <= (double)NX"),
-    "left edge excluded": ("u >= 0.0 && u < (double)NX", "u > 0.0 && u < (double)NX"),
-    "map transposed": ("return js * NX + is;", "return is * NY + js;"),
+    "closed window": ("u >= 0.0 && u < (double)W->NX", "u >= 0.0 && u <= (double)W->NX"),
+    "left edge excluded": ("u >= 0.0 && u < (double)W->NX", "u > 0.0 && u < (double)W->NX"),
+    "map transposed": ("return js * W->NX + is;", "return is * W->NY + js;"),
     "rounding instead of floor": ("int64_t is = (int64_t)floor(u);", "int64_t is = (int64_t)(u + 0.5);"),
-    "last star skipped": ("++k) {\n        double ex = tx - xs[k];\n        double ey = ty - ys[k];\n        double r2",
-                          "++k) {\n        if (k + 1 == n_stars) break;\n        double ex = tx - xs[k];\n"
-                          "        double ey = ty - ys[k];\n        double r2"),
+    "last star skipped": ("for (int64_t k = 0; k < L->n_stars; ++k) {",
+                          "for (int64_t k = 0; k + 1 < L->n_stars; ++k) {"),
+    # the error scale S that every per-ray beta tolerance is stated against
+    "error scale: m/r^2 for m/r": ("s += ms[k] / sqrt(ex * ex + ey * ey);", "s += ms[k] / (ex * ex + ey * ey);"),
+    "error scale: sum of |theta| components": ("double s = fmax(fabs(tx), fabs(ty)) + fmax(ax, ay);",
+                                               "double s = fabs(tx) + fabs(ty) + fmax(ax, ay);"),
+    "error scale: K theta without abs": ("double ay = fabs(gamma2 * tx + (kappa_c - gamma1) * ty);",
+                                         "double ay = (gamma2 * tx + (kappa_c - gamma1) * ty);"),
+    "error scale: theta without abs": ("fmax(fabs(tx), fabs(ty))", "fmax(tx, ty)"),
+    "error scale: star term dropped": ("s += ms[k] / sqrt(", "s += 0.0 * ms[k] / sqrt("),
 }
 
 
@@ -50,6 +57,8 @@ def _pin_suite(lib):
         ("conservation", lambda: pins.test_map_is_histogram_of_bins(lib)),
         ("mirror", lambda: pins.test_mirror_symmetry(lib)),
         ("bands", lambda: pins.test_band_additivity(lib)),
+        ("error scale", lambda: pins.test_error_scale_hand_computed(lib)),
+        ("error scale bound", lambda: pins.test_error_scale_bounds_beta(lib)),
     ]
     for name, fn in cases:
         try:

@@ -154,6 +154,54 @@ def test_ray_on_star_is_dropped(oracle_lib):
     assert n == np.count_nonzero(b >= 0) == 63
 
 
+# ----------------------------------------------------------------- error scale
+def test_error_scale_hand_computed(oracle_lib):
+    """S = |theta|_inf + |K theta|_inf + sum_k m_k / r_k, worked by hand.
+
+    kappa_c = 1/4, gamma = (1/8, 1/16), so K = [[3/8, 1/16], [1/16, 1/8]].
+    Ray A, theta = (1, -2): |theta|_inf = 2 (the negative component), K theta
+    = (1/4, -3/16), star 1 at (4, 2) with m = 2 sits at distance 5 (a 3-4-5
+    triangle): 2/5; star 2 at (1, -3/2) with m = 1/4 at distance 1/2: 1/2.
+    S = 2 + 1/4 + 2/5 + 1/2 = 3.15.  Ray B is A mirrored through the origin
+    (theta = (-1, 2), stars at (-4, -2) and (-1, 3/2)): K theta = (-1/4, 3/16),
+    whose larger magnitude is the negative component, and S = 3.15 again.
+    With m/r^2 in place of m/r S would be 3.33, with |theta|_1 4.15, and
+    without the absolute values 2.4 (ray A) or 3.0875 (ray B)."""
+    kc, g1, g2 = 0.25, 0.125, 0.0625
+    lens_a = (kc, g1, g2, [4.0, 1.0], [2.0, -1.5], [2.0, 0.25])
+    lens_b = (kc, g1, g2, [-4.0, -1.0], [-2.0, 1.5], [2.0, 0.25])
+    sa = oracle_lib.error_scale(lens_a, [1.0], [-2.0])[0]
+    sb = oracle_lib.error_scale(lens_b, [-1.0], [2.0])[0]
+    assert abs(sa - 3.15) <= 4e-16 * 3.15, sa
+    assert abs(sb - 3.15) <= 4e-16 * 3.15, sb
+    # no stars, theta = (0, -2): K theta = (-1/8, -1/4), the y component the
+    # larger in magnitude and negative; S = 2 + 1/4 exactly
+    s0 = oracle_lib.error_scale((kc, g1, g2, [], [], []), [0.0], [-2.0])[0]
+    assert s0 == 2.25
+
+
+def test_error_scale_bounds_beta(oracle_lib):
+    """|beta|_inf <= S for every ray (triangle inequality over the terms of
+    Eq. (2)-(3)), with equality when every term points the same way."""
+    rng = np.random.default_rng(31)
+    xs, ys = rng.uniform(-3, 3, 40), rng.uniform(-3, 3, 40)
+    ms = rng.uniform(0.05, 1.0, 40)
+    lens = (0.3, -0.2, 0.1, xs, ys, ms)
+    rays = (-4.0, -3.0, 8 / 37, 6 / 29, 37, 29, 0, 0)
+    bx, by, _ = oracle_lib.shoot(lens, rays, (-1.0, -1.0, 0.5, 0.5, 4, 4))
+    tx, ty = oracle_lib.image_angles(rays)
+    TX, TY = np.meshgrid(tx, ty)
+    s = oracle_lib.error_scale(lens, TX.ravel(), TY.ravel()).reshape(TX.shape)
+    assert np.all(np.maximum(np.abs(bx), np.abs(by)) <= s * (1 + 1e-14))
+    # every term aligned: theta = (2, 0), K theta = (-1, 0), star at (6, 0)
+    # with m = 1/2 (its term, m (theta - theta_k) / r^2 = (-1/8, 0), is also
+    # subtracted): beta_x = 2 + 1 + 1/8 = S, all in exact dyadic arithmetic
+    lens1 = (-0.5, 0.0, 0.0, [6.0], [0.0], [0.5])
+    bx1, by1, _ = oracle_lib.shoot(lens1, (1.5, -0.5, 1.0, 1.0, 1, 1, 0, 0), (-1.0, -1.0, 0.5, 0.5, 4, 4))
+    s1 = oracle_lib.error_scale(lens1, [2.0], [0.0])[0]
+    assert s1 == 3.125 and bx1[0, 0] == 3.125 and by1[0, 0] == 0.0
+
+
 # ----------------------------------------------------------------- exact brute force
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_exact_rational_brute_force(oracle_lib, seed):

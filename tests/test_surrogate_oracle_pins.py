@@ -5,11 +5,11 @@ import numpy as np
 import pytest
 
 from oracle import shooter as ora
-from oracle import surrogate as S
+from oracle import surrogate as S_REAL
 
 
 # ----------------------------------------------------------------- map -> histogram
-def test_magnification_of_a_sheet_is_inverse_determinant(oracle_lib):
+def pin_magnification_of_a_sheet_is_inverse_determinant(S):
     """No stars: the normalised counts equal 1/|det A| in every pixel far
     from the window edge (to lattice-counting error)."""
     kc, g1, g2 = 0.25, 0.125, 0.0
@@ -22,18 +22,18 @@ def test_magnification_of_a_sheet_is_inverse_determinant(oracle_lib):
     assert abs(mu.mean() * det - 1) < 2e-3
 
 
-@pytest.mark.parametrize("sigma,pixel", [(0.01, 0.0195), (0.1, 0.0195), (1.0, 0.0195), (0.3, 0.05)])
-def test_gaussian_taps(sigma, pixel):
-    g, r = S.gaussian_taps(sigma, pixel)
-    assert len(g) == 2 * r + 1 and r == math.ceil(3 * sigma / pixel)
-    assert abs(g.sum() - 1) < 1e-14
-    np.testing.assert_array_equal(g, g[::-1])
-    if sigma > 5 * pixel:   # the sampled variance is sigma^2 up to the truncation near 3 sigma
-        k = np.arange(-r, r + 1) * pixel
-        assert abs((g * k * k).sum() / sigma ** 2 - 1) < 0.04
+def pin_gaussian_taps(S):
+    for sigma, pixel in ((0.01, 0.0195), (0.1, 0.0195), (1.0, 0.0195), (0.3, 0.05)):
+        g, r = S.gaussian_taps(sigma, pixel)
+        assert len(g) == 2 * r + 1 and r == math.ceil(3 * sigma / pixel)
+        assert abs(g.sum() - 1) < 1e-14
+        np.testing.assert_array_equal(g, g[::-1])
+        if sigma > 5 * pixel:   # the sampled variance is sigma^2 up to the truncation near 3 sigma
+            k = np.arange(-r, r + 1) * pixel
+            assert abs((g * k * k).sum() / sigma ** 2 - 1) < 0.04
 
 
-def test_smooth_constant_delta_and_ramp():
+def pin_smooth_constant_delta_and_ramp(S):
     ny, nx, P, sigma = 40, 50, 0.1, 0.25
     out = S.smooth(np.full((ny, nx), 3.0), sigma, P, P)
     np.testing.assert_allclose(out, 3.0, rtol=1e-14)
@@ -50,7 +50,7 @@ def test_smooth_constant_delta_and_ramp():
     np.testing.assert_allclose(out, ramp[r:ny - r, r:nx - r], rtol=1e-13)
 
 
-def test_histogram_bins_of_known_values():
+def pin_histogram_bins_of_known_values(S):
     nb, lo, hi = 64, -2.0, 2.0
     mu_ref = 2.5
     vals = np.array([[0.0, mu_ref, 10 * mu_ref, 1e-3 * mu_ref, 1e3 * mu_ref, 0.999 * mu_ref]])
@@ -62,7 +62,7 @@ def test_histogram_bins_of_known_values():
 
 
 # ----------------------------------------------------------------- network
-def test_bf16_rounding_matches_torch():
+def pin_bf16_rounding_matches_torch(S):
     import torch
     rng = np.random.default_rng(0)
     a = (rng.standard_normal(20000) * 10.0 ** rng.uniform(-5, 5, 20000)).astype(np.float32)
@@ -73,7 +73,7 @@ def test_bf16_rounding_matches_torch():
     assert S.bf16_round(ties).tolist() == [1.0, 1.0 + 2 ** -6, -1.0, 3.0]
 
 
-def test_gelu_matches_torch_and_its_derivative():
+def pin_gelu_matches_torch_and_its_derivative(S):
     import torch
     z = np.linspace(-6, 6, 1001)
     want = torch.nn.functional.gelu(torch.from_numpy(z)).numpy()
@@ -84,7 +84,7 @@ def test_gelu_matches_torch_and_its_derivative():
     assert S.gelu(0.0) == 0.0 and S.gelu_grad(0.0) == 0.5
 
 
-def _tiny(seed=0, n_in=4, h=8, n_out=5, B=6):
+def _tiny(S, seed=0, n_in=4, h=8, n_out=5, B=6):
     rng = np.random.default_rng(seed)
     params = S.init_params(n_in, h, n_out, rng).astype(np.float64)
     params += rng.normal(0, 0.1, params.shape)   # non-zero biases too
@@ -94,8 +94,8 @@ def _tiny(seed=0, n_in=4, h=8, n_out=5, B=6):
     return params, x, t, (n_in, h, n_out)
 
 
-def test_gradients_match_finite_differences():
-    params, x, t, dims = _tiny()
+def pin_gradients_match_finite_differences(S):
+    params, x, t, dims = _tiny(S)
     g = S.gradients(params, x, t, *dims, weights_bf16=False)
     eps = 1e-6
     fd = np.empty_like(params)
@@ -108,8 +108,8 @@ def test_gradients_match_finite_differences():
     np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-9)
 
 
-def test_softmax_cross_entropy_special_cases():
-    params, x, _, dims = _tiny(1)
+def pin_softmax_cross_entropy_special_cases(S):
+    params, x, _, dims = _tiny(S, 1)
     p, _ = S.forward(params, x, *dims, weights_bf16=False)
     np.testing.assert_allclose(p.sum(axis=1), 1.0, rtol=1e-15)
     # target = prediction: the loss is the mean entropy and the gradient vanishes
@@ -121,9 +121,64 @@ def test_softmax_cross_entropy_special_cases():
     assert abs(S.loss(params, x, onehot, *dims, weights_bf16=False) - want) < 1e-13
 
 
-def test_adam_first_step_is_signed_learning_rate():
+def pin_adam_first_step_is_signed_learning_rate(S):
     g = np.array([3.0, -0.2, 1e-3, -7.0])
     p, m, v = S.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01, eps=0.0)
     np.testing.assert_allclose(p, -0.01 * np.sign(g), rtol=1e-14)
     np.testing.assert_allclose(m, 0.1 * g)
     np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def pin_adam_constant_gradient(S):
+    """A constant gradient g from the zero state: the moments are the
+    geometric sums m_t = (1 - beta1^t) g and v_t = (1 - beta2^t) g^2, so the
+    bias-corrected moments are exactly g and g^2 at every step and, with
+    eps = 0, every step moves each parameter by lr against the sign of its
+    gradient.  A beta1 and beta2 swapped anywhere in the recurrences or the
+    corrections breaks this from the second step on."""
+    g = np.array([3.0, -0.2, 1e-3, -7.0])
+    lr, b1, b2 = 0.01, 0.9, 0.999
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for t in range(1, 7):
+        p, m, v = S.adam(p, g, m, v, t, lr=lr, beta1=b1, beta2=b2, eps=0.0)
+        np.testing.assert_allclose(m, (1 - b1 ** t) * g, rtol=1e-13)
+        np.testing.assert_allclose(v, (1 - b2 ** t) * g * g, rtol=1e-12)
+        np.testing.assert_allclose(p, -lr * t * np.sign(g), rtol=1e-12)
+
+
+def pin_adam_three_steps_from_a_nonzero_state(S):
+    """Three steps with different gradients from a state (m0, v0) reached at
+    step 4: the moments equal their unrolled exponential averages
+    beta^n x0 + (1 - beta) sum_u beta^(n-u) g_u (a sum over the gradient
+    history, not the one-step recurrence), and each parameter update is
+    lr * mhat / (sqrt(vhat) + eps) with the bias corrections of steps 5, 6
+    and 7."""
+    rng = np.random.default_rng(12)
+    n = 7
+    p0 = rng.normal(0, 1, n)
+    m0 = rng.normal(0, 0.3, n)
+    v0 = rng.uniform(0.1, 2.0, n)
+    gs = [rng.normal(0, 1, n) for _ in range(3)]
+    lr, b1, b2, eps = 3e-3, 0.8, 0.95, 1e-6
+    p, m, v = p0, m0, v0
+    want_p = p0.copy()
+    for k in range(1, 4):
+        p, m, v = S.adam(p, gs[k - 1], m, v, 4 + k, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        mk = b1 ** k * m0 + (1 - b1) * sum(b1 ** (k - u) * gs[u - 1] for u in range(1, k + 1))
+        vk = b2 ** k * v0 + (1 - b2) * sum(b2 ** (k - u) * gs[u - 1] ** 2 for u in range(1, k + 1))
+        np.testing.assert_allclose(m, mk, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(v, vk, rtol=1e-12)
+        want_p = want_p - lr * (mk / (1 - b1 ** (4 + k))) / (np.sqrt(vk / (1 - b2 ** (4 + k))) + eps)
+        np.testing.assert_allclose(p, want_p, rtol=1e-12, atol=1e-15)
+
+
+PINS = [pin_magnification_of_a_sheet_is_inverse_determinant, pin_gaussian_taps, pin_smooth_constant_delta_and_ramp,
+        pin_histogram_bins_of_known_values, pin_bf16_rounding_matches_torch,
+        pin_gelu_matches_torch_and_its_derivative, pin_gradients_match_finite_differences,
+        pin_softmax_cross_entropy_special_cases, pin_adam_first_step_is_signed_learning_rate,
+        pin_adam_constant_gradient, pin_adam_three_steps_from_a_nonzero_state]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=lambda p: p.__name__)
+def test_pin(pin):
+    pin(S_REAL)
