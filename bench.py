@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--cpu-rays", type=int, default=1024, help="side of the oracle's ray sample (about 15 s)")
     ap.add_argument("--cpu-all-rays", type=int, default=2048,
                     help="side of the ray sample of the all-cores oracle run")
-    ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share (default: library's)")
+    ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share[,stars per group] (default: library's)")
     ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer 3 times (the reference kernel for "
@@ -342,8 +342,8 @@ def main():
     inter = w.interactions
     ctx = raysh.Context(w.lens, device=0)
     if args.tile:
-        cx, cy, sh = (int(v) for v in args.tile.split(","))
-        ctx.set_tile("fp64", cx, cy, share=sh)
+        t = [int(v) for v in args.tile.split(",")]
+        ctx.set_tile("fp64", t[0], t[1], share=t[2], star_tile=t[3] if len(t) > 3 else 0)
     if args.tile32:
         cx, cy, st = (int(v) for v in args.tile32.split(","))
         ctx.set_tile("fp32_bulk", cx, cy, star_tile=st)

@@ -139,12 +139,14 @@ int64_t raysh_n_stars(const raysh_ctx *ctx);
  * (the autotuner's knob; results do not depend on it beyond rounding for
  * RAYSH_FP64).  RAYSH_FP64_EXPANSION has one fixed shape; these calls, the
  * tuner and raysh_map_batch return EINVAL for it.  Each lane of a
- * 256-lane workgroup owns cx x cy rays of a (16 cx) x (16 cy) ray tile;
- * `share` stars share one reciprocal in the FP64 star sum; `star_tile`
- * stars are staged in LDS per pass in the FP32-bulk sum (the FP32 partial
- * sums are flushed into FP64 after each pass).  Fields that do not apply to
- * the precision are ignored by raysh_get_tile callers and must be 0 in
- * raysh_set_tile.  EINVAL if the shape is not compiled into the library.
+ * 256-lane workgroup owns cx x cy rays of a (16 cx) x (16 cy) ray tile.
+ * RAYSH_FP64: `share` values of r^2 share one reciprocal (a product tree,
+ * refined by a Newton step); `star_tile` of them (1, 2 or 4) are consecutive
+ * stars of one ray, the rest neighbouring rays of the lane (star_tile 0 in
+ * raysh_set_tile means min(share, 4)).  RAYSH_FP32_BULK: `star_tile` stars
+ * are staged in LDS per pass (the FP32 partial sums are flushed into FP64
+ * after each pass), and `share` must be 0.  EINVAL if the shape is not
+ * compiled into the library.
  */
 int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int star_tile);
 

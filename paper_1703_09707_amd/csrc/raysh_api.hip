@@ -367,9 +367,9 @@ int64_t raysh_n_stars(const raysh_ctx *ctx) { return ctx ? ctx->n_stars : 0; }
 int raysh_set_tile(raysh_ctx *ctx, int precision, int cx, int cy, int share, int star_tile) {
     if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
     if (int r = validate_tiled_precision(precision)) return r;
-    if ((precision == RAYSH_FP64 && star_tile != 0) || (precision == RAYSH_FP32_BULK && share != 0))
-        return set_error(RAYSH_EINVAL, "a tile field that does not apply to precision %d is not 0",
-                         precision);
+    if (precision == RAYSH_FP32_BULK && share != 0)
+        return set_error(RAYSH_EINVAL, "share does not apply to RAYSH_FP32_BULK and must be 0");
+    if (precision == RAYSH_FP64 && star_tile == 0) star_tile = share < 4 ? share : 4;   // stars per group
     TileShape t{cx, cy, share, star_tile};
     const bool supported = precision == RAYSH_FP64 ? raysh::fp64_shape_supported(t)
                                                    : raysh::fp32_shape_supported(t);

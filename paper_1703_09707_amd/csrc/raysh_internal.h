@@ -58,8 +58,9 @@ struct BatchArgs {
 // Launch shapes selectable per call (the autotuner's search space).
 struct TileShape {
     int cx, cy;      // rays per lane along x and y
-    int share;       // stars sharing one reciprocal (FP64 path)
-    int star_tile;   // stars staged in LDS per pass (FP32-bulk path)
+    int share;       // r^2 values sharing one reciprocal (FP64 path)
+    int star_tile;   // FP64: consecutive stars among them (the rest are the lane's
+                     // neighbouring rays); FP32-bulk: stars staged in LDS per pass
 };
 
 // Launchers (shoot_fp64.hip, shoot_fp32.hip).  Return hipSuccess or the

@@ -14,16 +14,18 @@
 //
 // The division m_k / r_k^2 of Eq. (3) uses the hardware reciprocal, which
 // is good to about 2^-24 and issues at a quarter of the FMA rate, refined by
-// one Newton step.  SHARE values of r^2 share one reciprocal: up to four
-// consecutive stars of one ray, or four stars times two neighbouring rays of
-// a row; 1/r^2 of each is recovered from the reciprocal of their product
-// through a product tree (for two: y = 1/(r_a^2 r_b^2), 1/r_a^2 = r_b^2 y,
-// 1/r_b^2 = r_a^2 y).  The relative error of each 1/r^2 is a few units in
-// the last place of FP64 (the refined reciprocal is good to about 2^-48).
-// The product of eight r^2 stays in FP64 range for separations between
-// about 1e-19 and 1e19.  A ray exactly on a star gets a zero product, an
-// infinite or NaN weight and a non-finite beta, and is dropped, as the plain
-// definition drops it.
+// one Newton step.  SHARE values of r^2 share one reciprocal: NS consecutive
+// stars of one ray times GX x GY of the lane's rays (for instance one star
+// and the eight rays of a lane row); 1/r^2 of each is recovered from the
+// reciprocal of their product through a product tree (for two:
+// y = 1/(r_a^2 r_b^2), 1/r_a^2 = r_b^2 y, 1/r_b^2 = r_a^2 y).  The relative
+// error of each 1/r^2 is a few units in the last place of FP64 (the refined
+// reciprocal is good to about 2^-48).  A ray exactly on a star makes the
+// shared product zero and its partners' weights NaN, and separations far
+// outside [1e-19, 1e19] take the product out of FP64 range; rays that end
+// with a non-finite sum are therefore summed again one by one with a
+// division per star, so that only a ray that sits on a star is dropped, as
+// the plain definition drops it.
 // The mass multiplies either the per-column and per-row offsets (when a lane
 // owns more rays than it has rows plus columns) or 1/r^2 of each ray; the
 // accumulation alpha += (m/r^2)(theta - theta_k) is one FMA per component,
@@ -73,20 +75,27 @@ __device__ __forceinline__ double mul_rn(double a, double b) {
     return a * b;
 }
 
+// How the SHARE values of r^2 that share one reciprocal are chosen: NS
+// consecutive stars, times GX columns of the lane's rays, times GY rows.
+template <int CX, int CY, int SHARE, int NS>
+struct Grouping {
+    static constexpr int GX = (SHARE / NS) < CX ? (SHARE / NS) : CX;
+    static constexpr int GY = SHARE / (NS * GX);
+    static_assert(NS >= 1 && NS <= 4 && NS * GX * GY == SHARE && CX % GX == 0 && CY % GY == 0,
+                  "SHARE = NS stars x GX columns x GY rows of the lane's rays");
+};
+
 // The second term of Eq. (3) for stars [k0, k1) of a lane's CX x CY rays,
-// added to (ax, ay) in star index order.
-template <int CX, int CY, int SHARE>
+// added to (ax, ay) in star index order.  Each reciprocal is shared by NS
+// consecutive stars times GX x GY of the lane's rays.
+template <int CX, int CY, int NS, int GX, int GY>
 __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, const double (&tx)[CX],
                                          const double (&ty)[CY], double (&ax)[CY][CX],
                                          double (&ay)[CY][CX]) {
     // Fold the mass into the per-column and per-row offsets when that takes
     // fewer multiplies (CX + CY per star) than weighting every ray (CX * CY).
     constexpr bool FOLD = CX * CY > CX + CY;
-    // SHARE factors r^2 share one reciprocal: NS stars times RG neighbouring
-    // rays of a row (RG = 2 once more than 4 factors share it).
-    constexpr int NS = SHARE > 4 ? 4 : SHARE;
-    constexpr int RG = SHARE / NS;
-    static_assert(NS * RG == SHARE && CX % RG == 0, "SHARE = NS stars x RG rays");
+    constexpr int G = NS * GX * GY;
     int k = k0;
     // star groups are double-buffered: the next group's scalar loads are in
     // flight while the current group is computed (the index of the group
@@ -128,24 +137,32 @@ __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, co
             }
         }
 #pragma unroll
-        for (int b = 0; b < CY; ++b) {
+        for (int b0 = 0; b0 < CY; b0 += GY) {
 #pragma unroll
-            for (int a0 = 0; a0 < CX; a0 += RG) {
-                // RG neighbouring rays of the row and NS stars share one reciprocal
-                double r2[RG * NS], inv[RG * NS];
+            for (int a0 = 0; a0 < CX; a0 += GX) {
+                // GX x GY rays of the lane and NS stars share one reciprocal
+                double r2[G], inv[G];
 #pragma unroll
-                for (int g = 0; g < RG; ++g)
+                for (int gy = 0; gy < GY; ++gy)
 #pragma unroll
-                    for (int s = 0; s < NS; ++s)
-                        r2[g * NS + s] = __builtin_fma(ex[s][a0 + g], ex[s][a0 + g], ey2[s][b]);
-                reciprocals<RG * NS>(r2, inv);
+                    for (int gx = 0; gx < GX; ++gx)
 #pragma unroll
-                for (int g = 0; g < RG; ++g) {
+                        for (int s = 0; s < NS; ++s)
+                            r2[(gy * GX + gx) * NS + s] =
+                                __builtin_fma(ex[s][a0 + gx], ex[s][a0 + gx], ey2[s][b0 + gy]);
+                reciprocals<G>(r2, inv);
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) {
-                        const double w = FOLD ? inv[g * NS + s] : sm[s] * inv[g * NS + s];
-                        ax[b][a0 + g] = __builtin_fma(w, mex[s][a0 + g], ax[b][a0 + g]);
-                        ay[b][a0 + g] = __builtin_fma(w, mey[s][b], ay[b][a0 + g]);
+                for (int gy = 0; gy < GY; ++gy) {
+#pragma unroll
+                    for (int gx = 0; gx < GX; ++gx) {
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) {
+                            const int a = a0 + gx, b = b0 + gy;
+                            const double inv1 = inv[(gy * GX + gx) * NS + s];
+                            const double w = FOLD ? inv1 : sm[s] * inv1;
+                            ax[b][a] = __builtin_fma(w, mex[s][a], ax[b][a]);
+                            ay[b][a] = __builtin_fma(w, mey[s][b], ay[b][a]);
+                        }
                     }
                 }
             }
@@ -160,21 +177,98 @@ __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, co
             asm volatile("" : "=s"(sm[s]) : "0"(nm[s]));
         }
     }
-    for (; k < k1; ++k) {   // remaining stars, one at a time, still in index order
-        const double sx1 = st[k].x, sy1 = st[k].y, sm1 = st[k].m;
+    if constexpr (NS > 1) {
+        for (; k < k1; ++k) {   // remaining stars, one at a time, still in index order
+            const double sx1 = st[k].x, sy1 = st[k].y, sm1 = st[k].m;
 #pragma unroll
-        for (int b = 0; b < CY; ++b) {
-            const double ey = ty[b] - sy1;
-            const double ey2 = mul_rn(ey, ey);
+            for (int b = 0; b < CY; ++b) {
+                const double ey = ty[b] - sy1;
+                const double ey2 = mul_rn(ey, ey);
 #pragma unroll
-            for (int a = 0; a < CX; ++a) {
-                const double ex = tx[a] - sx1;
-                double r2[1] = {__builtin_fma(ex, ex, ey2)}, inv[1];
-                reciprocals<1>(r2, inv);
-                const double w = sm1 * inv[0];
-                ax[b][a] = __builtin_fma(w, ex, ax[b][a]);
-                ay[b][a] = __builtin_fma(w, ey, ay[b][a]);
+                for (int a = 0; a < CX; ++a) {
+                    const double ex = tx[a] - sx1;
+                    double r2[1] = {__builtin_fma(ex, ex, ey2)}, inv[1];
+                    reciprocals<1>(r2, inv);
+                    const double w = sm1 * inv[0];
+                    ax[b][a] = __builtin_fma(w, ex, ax[b][a]);
+                    ay[b][a] = __builtin_fma(w, ey, ay[b][a]);
+                }
             }
+        }
+    }
+}
+
+// True in every lane of the wave when any lane holds a non-finite sum.
+template <int CX, int CY>
+__device__ __forceinline__ bool wave_any_nonfinite(const double (&ax)[CY][CX], const double (&ay)[CY][CX]) {
+    bool bad = false;
+#pragma unroll
+    for (int b = 0; b < CY; ++b)
+#pragma unroll
+        for (int a = 0; a < CX; ++a) bad |= !__builtin_isfinite(ax[b][a]) || !__builtin_isfinite(ay[b][a]);
+    return __builtin_amdgcn_ballot_w64(bad) != 0;
+}
+
+// Stars [k0, k1) of one ray, added to (ax, ay) in index order with an IEEE
+// division per star (the cold path below).
+__device__ __forceinline__ void direct_star_sum(const ConstStar *st, int k0, int k1, double tx, double ty,
+                                                double &ax, double &ay) {
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k) {
+        const double ex = tx - st[k].x, ey = ty - st[k].y;
+        const double w = st[k].m / __builtin_fma(ex, ex, mul_rn(ey, ey));
+        ax = __builtin_fma(w, ex, ax);
+        ay = __builtin_fma(w, ey, ay);
+    }
+}
+
+// Stars [k0, k1) of the lane's rays, added to (ax, ay), which hold the macro
+// term K theta (MACRO: one pass) or zero (a part of a split sum).  When
+// several rays share a reciprocal, a ray exactly on a star (r^2 = 0) turns
+// the shared product into zero and the weights of its partners into NaN, and
+// separations beyond the product's FP64 range do the same.  So every ray that
+// ends with a non-finite sum is summed again on its own, with a division per
+// star: then only a ray that sits on a star stays non-finite (and is dropped,
+// as in the definition).  That cold path goes through a private array indexed
+// at run time, so that it claims no registers of the main loop.
+template <int CX, int CY, int SHARE, int NS, bool MACRO>
+__device__ __forceinline__ void lane_star_sums(const ShootParams &p, const ConstStar *st, int k0, int k1,
+                                               const double (&tx)[CX], const double (&ty)[CY],
+                                               double (&ax)[CY][CX], double (&ay)[CY][CX]) {
+    using Gr = Grouping<CX, CY, SHARE, NS>;
+    star_sum<CX, CY, NS, Gr::GX, Gr::GY>(st, k0, k1, tx, ty, ax, ay);
+    if constexpr (SHARE > 1) {
+        if (wave_any_nonfinite<CX, CY>(ax, ay)) {   // uniform across the wave
+            double sum[2][CY * CX], ptx[CX], pty[CY];
+#pragma unroll
+            for (int a = 0; a < CX; ++a) ptx[a] = tx[a];
+#pragma unroll
+            for (int b = 0; b < CY; ++b) pty[b] = ty[b];
+#pragma unroll
+            for (int b = 0; b < CY; ++b)
+#pragma unroll
+                for (int a = 0; a < CX; ++a) {
+                    sum[0][b * CX + a] = ax[b][a];
+                    sum[1][b * CX + a] = ay[b][a];
+                }
+#pragma unroll 1
+            for (int r = 0; r < CX * CY; ++r) {
+                if (!__builtin_isfinite(sum[0][r]) || !__builtin_isfinite(sum[1][r])) {
+                    const double rx = ptx[r % CX], ry = pty[r / CX];
+                    double x = 0.0, y = 0.0;
+                    if constexpr (MACRO) macro_term(p, rx, ry, x, y);
+                    direct_star_sum(st, k0, k1, rx, ry, x, y);
+                    sum[0][r] = x;
+                    sum[1][r] = y;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < CY; ++b)
+#pragma unroll
+                for (int a = 0; a < CX; ++a) {
+                    ax[b][a] = sum[0][b * CX + a];
+                    ay[b][a] = sum[1][b * CX + a];
+                }
         }
     }
 }
@@ -197,7 +291,7 @@ __device__ __forceinline__ void tile_rays(const ShootParams &p, int64_t tile, do
 
 // One ray tile (all of Algorithm 1 for its rays).  sh.red must be zero on
 // entry; every thread of the workgroup must call it.
-template <int CX, int CY, int SHARE>
+template <int CX, int CY, int SHARE, int NS>
 __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, int64_t tile) {
     double tx[CX], ty[CY];
     int64_t tile_i, tile_j;
@@ -208,15 +302,16 @@ __device__ __forceinline__ void fp64_tile(const ShootParams &p, BinShared &sh, i
     for (int b = 0; b < CY; ++b)
 #pragma unroll
         for (int a = 0; a < CX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
-    star_sum<CX, CY, SHARE>(const_stars(uniform_ptr(p.stars)), 0, uniform(p.n_stars), tx, ty, ax, ay);
+    lane_star_sums<CX, CY, SHARE, NS, true>(p, const_stars(uniform_ptr(p.stars)), 0, uniform(p.n_stars), tx, ty,
+                                            ax, ay);
     finish_tile<CX, CY>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
 }
 
-template <int CX, int CY, int SHARE>
-__global__ __launch_bounds__(kThreads) void shoot_fp64_kernel(ShootParams p) {
+template <int CX, int CY, int SHARE, int NS>
+__global__ __launch_bounds__(kThreads, 2) void shoot_fp64_kernel(ShootParams p) {
     __shared__ BinShared sh;
     bin_shared_init(sh);
-    fp64_tile<CX, CY, SHARE>(p, sh, blockIdx.x);
+    fp64_tile<CX, CY, SHARE, NS>(p, sh, blockIdx.x);
 }
 
 // Persistent form: workgroups take items (runs of ray tiles of one set)
@@ -225,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void shoot_fp64_kernel(ShootParams p) {
 // two waves per SIMD are requested: the queue loop keeps a few more values
 // live than one tile does, and the compiler would otherwise give up the
 // second wave for them.
-template <int CX, int CY, int SHARE>
+template <int CX, int CY, int SHARE, int NS>
 __global__ __launch_bounds__(kThreads, 2) void batch_fp64_kernel(BatchArgs b) {
     __shared__ BinShared sh;
     __shared__ BatchSet s_set;
@@ -244,7 +339,7 @@ __global__ __launch_bounds__(kThreads, 2) void batch_fp64_kernel(BatchArgs b) {
         const int64_t n_tiles = uniform64(s_set.n_tiles);
         const int64_t t1 = t0 + per < n_tiles ? t0 + per : n_tiles;
         for (int64_t t = t0; t < t1; ++t) {   // uniform trip count
-            fp64_tile<CX, CY, SHARE>(s_set.p, sh, t);
+            fp64_tile<CX, CY, SHARE, NS>(s_set.p, sh, t);
             __syncthreads();   // red and the window are reused
             bin_shared_init(sh);
         }
@@ -257,8 +352,8 @@ __global__ __launch_bounds__(kThreads, 2) void batch_fp64_kernel(BatchArgs b) {
 // the tile's rays into partial[part][ray] (FP64 pairs, ray = j*nx + i of
 // the block).  Blocks are numbered part-major, so blocks running together
 // share their stars in the caches.
-template <int CX, int CY, int SHARE>
-__global__ __launch_bounds__(kThreads) void partial_fp64_kernel(ShootParams p, int64_t n_tiles, int chunk,
+template <int CX, int CY, int SHARE, int NS>
+__global__ __launch_bounds__(kThreads, 2) void partial_fp64_kernel(ShootParams p, int64_t n_tiles, int chunk,
                                                                 double2 *__restrict__ partial) {
     const int part = (int)(blockIdx.x / n_tiles);
     const int64_t tile = blockIdx.x % n_tiles;
@@ -275,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void partial_fp64_kernel(ShootParams p, i
     const int64_t first = (int64_t)part * chunk;
     const int k0 = (int)(first < n ? first : n);
     const int k1 = (int)(k0 + (int64_t)chunk < n ? k0 + (int64_t)chunk : n);
-    star_sum<CX, CY, SHARE>(const_stars(uniform_ptr(p.stars)), k0, k1, tx, ty, ax, ay);
+    lane_star_sums<CX, CY, SHARE, NS, false>(p, const_stars(uniform_ptr(p.stars)), k0, k1, tx, ty, ax, ay);
     const int64_t n_rays = p.nx * p.ny;
 #pragma unroll
     for (int b = 0; b < CY; ++b) {
@@ -320,42 +415,41 @@ __global__ __launch_bounds__(kThreads) void finish_fp64_kernel(ShootParams p, in
     finish_tile<CX, CY>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
 }
 
-template <int CX, int CY, int SHARE>
+template <int CX, int CY, int SHARE, int NS>
 hipError_t launch_batch(const BatchArgs &b, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((batch_fp64_kernel<CX, CY, SHARE>), dim3(blocks), dim3(kThreads), 0, s, b);
+    hipLaunchKernelGGL((batch_fp64_kernel<CX, CY, SHARE, NS>), dim3(blocks), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 
-template <int CX, int CY, int SHARE>
+template <int CX, int CY, int SHARE, int NS>
 int batch_blocks_per_cu() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_fp64_kernel<CX, CY, SHARE>, kThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_fp64_kernel<CX, CY, SHARE, NS>, kThreads, 0) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 
-template <int CX, int CY, int SHARE>
+template <int CX, int CY, int SHARE, int NS>
 hipError_t launch(const ShootParams &p, hipStream_t s) {
     const int64_t tiles_y = (p.ny + kLanesY * CY - 1) / (kLanesY * CY);
     ShootParams q = p;
     q.tiles_x = (int32_t)((p.nx + kLanesX * CX - 1) / (kLanesX * CX));
     const int64_t blocks = (int64_t)q.tiles_x * tiles_y;
-    hipLaunchKernelGGL((shoot_fp64_kernel<CX, CY, SHARE>), dim3((unsigned)blocks), dim3(kThreads),
+    hipLaunchKernelGGL((shoot_fp64_kernel<CX, CY, SHARE, NS>), dim3((unsigned)blocks), dim3(kThreads),
                        0, s, q);
     return hipGetLastError();
 }
 
-template <int CX, int CY, int SHARE>
+template <int CX, int CY, int SHARE, int NS>
 hipError_t launch_split(const ShootParams &p, int parts, double2 *partial, hipStream_t s) {
     ShootParams q = p;
     q.tiles_x = (int32_t)((p.nx + kLanesX * CX - 1) / (kLanesX * CX));
     const int64_t tiles_y = (p.ny + kLanesY * CY - 1) / (kLanesY * CY);
     const int64_t n_tiles = (int64_t)q.tiles_x * tiles_y;
-    constexpr int NS = SHARE > 4 ? 4 : SHARE;
     int chunk = (int)((p.n_stars + parts - 1) / parts);
     chunk = (chunk + NS - 1) / NS * NS;
-    hipLaunchKernelGGL((partial_fp64_kernel<CX, CY, SHARE>), dim3((unsigned)(n_tiles * parts)), dim3(kThreads),
+    hipLaunchKernelGGL((partial_fp64_kernel<CX, CY, SHARE, NS>), dim3((unsigned)(n_tiles * parts)), dim3(kThreads),
                        0, s, q, n_tiles, chunk, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -366,22 +460,29 @@ hipError_t launch_split(const ShootParams &p, int parts, double2 *partial, hipSt
 
 }  // namespace
 
+// Compiled launch shapes (CX, CY, SHARE, NS): rays per lane along x and y,
+// r^2 values per reciprocal, consecutive stars among them.
 #define RAYSH_FP64_SHAPES(X) \
-    X(1, 4, 2)               \
-    X(2, 2, 2)               \
-    X(2, 4, 4)               \
-    X(2, 4, 8)               \
-    X(4, 2, 4)               \
-    X(4, 2, 8)               \
-    X(4, 4, 2)               \
-    X(4, 4, 4)               \
-    X(4, 4, 8)               \
-    X(2, 8, 2)
+    X(1, 4, 2, 2)            \
+    X(2, 2, 2, 2)            \
+    X(2, 4, 4, 4)            \
+    X(2, 4, 8, 4)            \
+    X(4, 2, 4, 4)            \
+    X(4, 2, 8, 4)            \
+    X(4, 4, 2, 2)            \
+    X(4, 4, 4, 4)            \
+    X(4, 4, 8, 4)            \
+    X(2, 8, 2, 2)            \
+    X(4, 4, 8, 1)            \
+    X(4, 4, 16, 1)           \
+    X(8, 2, 8, 1)            \
+    X(8, 4, 8, 1)            \
+    X(4, 8, 8, 1)
 
 int fp64_shape_list(TileShape *out, int cap) {
     int n = 0;
-#define RAYSH_CASE(CX, CY, S)                          \
-    if (n < cap) out[n] = TileShape{CX, CY, S, 0}; \
+#define RAYSH_CASE(CX, CY, S, NS)                       \
+    if (n < cap) out[n] = TileShape{CX, CY, S, NS}; \
     ++n;
     RAYSH_FP64_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
@@ -389,16 +490,16 @@ int fp64_shape_list(TileShape *out, int cap) {
 }
 
 bool fp64_shape_supported(const TileShape &t) {
-#define RAYSH_CASE(CX, CY, S) \
-    if (t.cx == CX && t.cy == CY && t.share == S) return true;
+#define RAYSH_CASE(CX, CY, S, NS) \
+    if (t.cx == CX && t.cy == CY && t.share == S && t.star_tile == NS) return true;
     RAYSH_FP64_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
     return false;
 }
 
 hipError_t launch_shoot_fp64(const ShootParams &p, const TileShape &t, hipStream_t s) {
-#define RAYSH_CASE(CX, CY, S) \
-    if (t.cx == CX && t.cy == CY && t.share == S) return launch<CX, CY, S>(p, s);
+#define RAYSH_CASE(CX, CY, S, NS) \
+    if (t.cx == CX && t.cy == CY && t.share == S && t.star_tile == NS) return launch<CX, CY, S, NS>(p, s);
     RAYSH_FP64_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
     return hipErrorInvalidValue;
@@ -406,24 +507,27 @@ hipError_t launch_shoot_fp64(const ShootParams &p, const TileShape &t, hipStream
 
 hipError_t launch_split_fp64(const ShootParams &p, const TileShape &t, int parts, double2 *partial,
                              hipStream_t s) {
-#define RAYSH_CASE(CX, CY, S) \
-    if (t.cx == CX && t.cy == CY && t.share == S) return launch_split<CX, CY, S>(p, parts, partial, s);
+#define RAYSH_CASE(CX, CY, S, NS)                                          \
+    if (t.cx == CX && t.cy == CY && t.share == S && t.star_tile == NS) \
+        return launch_split<CX, CY, S, NS>(p, parts, partial, s);
     RAYSH_FP64_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_fp64(const BatchArgs &b, const TileShape &t, int blocks, hipStream_t s) {
-#define RAYSH_CASE(CX, CY, S) \
-    if (t.cx == CX && t.cy == CY && t.share == S) return launch_batch<CX, CY, S>(b, blocks, s);
+#define RAYSH_CASE(CX, CY, S, NS)                                          \
+    if (t.cx == CX && t.cy == CY && t.share == S && t.star_tile == NS) \
+        return launch_batch<CX, CY, S, NS>(b, blocks, s);
     RAYSH_FP64_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
     return hipErrorInvalidValue;
 }
 
 int batch_fp64_blocks_per_cu(const TileShape &t) {
-#define RAYSH_CASE(CX, CY, S) \
-    if (t.cx == CX && t.cy == CY && t.share == S) return batch_blocks_per_cu<CX, CY, S>();
+#define RAYSH_CASE(CX, CY, S, NS)                                          \
+    if (t.cx == CX && t.cy == CY && t.share == S && t.star_tile == NS) \
+        return batch_blocks_per_cu<CX, CY, S, NS>();
     RAYSH_FP64_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
     return 1;

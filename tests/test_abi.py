@@ -35,7 +35,10 @@ def test_compiled_tile_lists():
     f64 = R.list_tiles("fp64")
     f32 = R.list_tiles("fp32_bulk")
     assert len(f64) >= 5 and len(f32) >= 5
-    assert all(t[3] == 0 and t[2] in (1, 2, 4, 8) for t in f64)
+    # FP64: share in (2, 4, 8, 16) r^2 values per reciprocal, of which t[3]
+    # (1, 2 or 4) are consecutive stars; the rest are rays of the lane
+    assert all(t[2] in (2, 4, 8, 16) and t[3] in (1, 2, 4) and t[2] % t[3] == 0 for t in f64)
+    assert all(t[2] // t[3] <= t[0] * t[1] for t in f64)
     assert all(t[2] == 0 and t[3] > 0 for t in f32)
     lib = R.load()
     assert lib.raysh_list_tiles(5, None, 0) == -R.EINVAL
