@@ -13,10 +13,19 @@ FLOPs (10 per interaction: 2 subtractions, 2 multiplies and 1 add for r^2,
 peak; the kernel's own time comes from HIP events recorded on the stream the
 kernel runs on.
 
-Also reported: the 64-set batch in one graph-captured persistent launch
-(against single launches), the FP32-bulk misbinned fraction on the
-262144-star precision-study subtile, and the split star sum on 4194304 stars
-x 256^2 rays (against one pass per ray).
+Launch shapes come from the library's autotuner (raysh_autotune, and
+raysh_autotune_batch for the batch), run before the timed regions; the
+chosen shapes are reported.  Secondary sections are timed as the median of
+five runs after a warm-up.
+
+Also reported: the FP32-bulk form with its roofline against the non-packed
+FP32 vector peak and its misbinned fraction ray by ray against FP64, the
+64-set batch in one graph-captured persistent launch (against single
+launches, with the FP32-bulk misbinned fraction per set), the FP32-bulk
+misbinned fraction on the 262144-star precision-study subtile, the split
+star sum on 4194304 stars x 256^2 rays (against one pass per ray), the
+far-field expansion, light curves, the learned surrogate and the oracle on
+the host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
                        [--no-batch] [--no-precision] [--no-split]
@@ -34,6 +43,10 @@ FLOP_PER_INTERACTION = 10
 PROFILE = os.path.join(ROOT, "profiles", "shoot_fp64_kernel_plain-fp64-large.txt")
 PROFILE_LC = os.path.join(ROOT, "profiles", "light_curve_track_kernel_light-curves-large.txt")
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# FP32 without packed instructions (not used by this build) issues at the FP64 rate
+FP32_VECTOR_PEAK_TFLOPS = 78.6
+PROFILE_FP32 = os.path.join(ROOT, "profiles", "shoot_fp32_kernel_plain-fp64-large.txt")
+METRIC = "Gray-star interactions/s and rays/s at 1 GPU (FP64 vs FP32-bulk), % vector peak"
 HBM_PEAK_GBS = 8000.0              # MI355X HBM3E
 
 
@@ -56,6 +69,13 @@ def parse():
                     help="side of the ray sample of the all-cores oracle run")
     ap.add_argument("--tile", default=None, help="FP64 tile cx,cy,share[,stars per group] (default: library's)")
     ap.add_argument("--tile32", default=None, help="FP32-bulk tile cx,cy,star_tile")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
+    ap.add_argument("--no-per-ray", action="store_true",
+                    help="compare FP32-bulk with FP64 by maps only (no per-ray bins; for counter runs, so that "
+                         "every dispatch of the map kernels at full size is a map)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, always timed)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate section")
+    ap.add_argument("--runs", type=int, default=5, help="runs per secondary timing (median reported)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer 3 times (the reference kernel for "
                          "scaling HBM byte counters)")
@@ -93,62 +113,93 @@ def time_steps(torch, ctx, w, precision, counts, steps, warmup):
     return wall, kernel_ms
 
 
-def batch_section(torch, raysh, W):
+def median_seconds(torch, fn, runs, warm=1):
+    """Median wall time of fn() over `runs` runs after `warm` untimed ones,
+    each bracketed by device synchronisations; returns (median, all)."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2], ts
+
+
+def misbinned_lower_bound(a, b, n_rays):
+    """Rays in a different pixel, at least: half the L1 distance of two maps
+    plus half the change of the binned total, over the rays shot."""
+    l1 = int((a.long() - b.long()).abs().sum())
+    dn = abs(int(a.long().sum()) - int(b.long().sum()))
+    return 0.5 * (l1 + dn) / n_rays
+
+
+def batch_section(torch, raysh, W, runs, tune, cache):
     """64 parameter sets of uneven star counts in one persistent,
-    graph-captured launch (replayed), against one single launch per set."""
+    graph-captured launch (replayed), against one single launch per set; the
+    launch shape of each precision chosen by raysh_autotune_batch."""
     sets = W.batch_workloads()
     ctxs = [raysh.Context(x.lens) for x in sets]
     rays = [x.rays for x in sets]
     pix = [x.pix for x in sets]
     inter = sum(x.interactions for x in sets)
+    n_rays = sum(x.rays.n_rays for x in sets)
     out = {"workload": "batch-64: 64 sets x 4096^2 rays, 512^2 maps, N* %d..%d" % (
         min(x.lens.n_stars for x in sets), max(x.lens.n_stars for x in sets)),
-        "interactions": inter}
+        "interactions": inter, "rays": n_rays, "runs": runs}
+    maps = {}
     for prec in ("fp64", "fp32_bulk"):
-        maps = [torch.zeros((p.NY, p.NX), dtype=torch.int32, device="cuda") for p in pix]
-        raysh.map_batch(ctxs, rays, pix, prec, counts=maps)      # builds and captures the graph
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        raysh.map_batch(ctxs, rays, pix, prec, counts=maps)      # replay
+        tile = raysh.autotune_batch(ctxs, rays, pix, prec, cache) if tune else ctxs[0].get_tile(prec)
+        t_tune = time.perf_counter() - t0
+        m = [torch.zeros((p.NY, p.NX), dtype=torch.int32, device="cuda") for p in pix]
+        raysh.map_batch(ctxs, rays, pix, prec, counts=m)      # builds and captures the graph
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        out[prec] = {"value": inter / dt, "unit": "interactions/s", "seconds": dt,
-                     "tile": list(ctxs[0].get_tile(prec))}
-    t0 = time.perf_counter()
-    for c, x, p in zip(ctxs, rays, pix):
-        c.map(x, p, "fp64")
-    torch.cuda.synchronize()
-    single = time.perf_counter() - t0
-    out["fp64_single_launches"] = {"value": inter / single, "unit": "interactions/s", "seconds": single}
+        maps[prec] = [x.clone() for x in m]
+        dt, all_t = median_seconds(torch, lambda: raysh.map_batch(ctxs, rays, pix, prec, counts=m), runs, warm=0)
+        out[prec] = {"value": inter / dt, "unit": "interactions/s", "rays_per_s": n_rays / dt, "seconds": dt,
+                     "seconds_all": all_t, "tile": list(tile), "tune_seconds": t_tune,
+                     "roofline_frac": FLOP_PER_INTERACTION * inter / dt / 1e12 / (
+                         FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS)}
+    fr = [misbinned_lower_bound(a, b, x.rays.n_rays) for a, b, x in zip(maps["fp64"], maps["fp32_bulk"], sets)]
+    out["fp32_bulk"]["misbinned_fraction_vs_fp64_per_set"] = {"max": max(fr), "mean": sum(fr) / len(fr),
+                                                              "bound": "lower bound from each set's maps"}
+    del maps
+
+    def singles():
+        for c, x, p in zip(ctxs, rays, pix):
+            c.map(x, p, "fp64")
+    single, all_t = median_seconds(torch, singles, runs)
+    out["fp64_single_launches"] = {"value": inter / single, "unit": "interactions/s", "seconds": single,
+                                   "seconds_all": all_t, "tile": list(ctxs[0].get_tile("fp64"))}
     out["speedup_vs_plain_fp64"] = {p: single / out[p]["seconds"] for p in ("fp64", "fp32_bulk")}
     for c in ctxs:
         c.close()
     return out
 
 
-def precision_section(torch, raysh, W):
+def precision_section(torch, raysh, W, runs):
     """FP32-bulk against FP64, ray by ray, on the central 2048^2 rays of the
     262144-star precision-study lattice."""
     w = W.precision_study()
     sub = W.precision_subtile(w, 2048)
     with raysh.Context(w.lens) as ctx:
         _, _, b64 = ctx.shoot(sub, "fp64", w.pix, beta=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         _, _, b32 = ctx.shoot(sub, "fp32_bulk", w.pix, beta=False)
-        torch.cuda.synchronize()
-        t32 = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        ctx.shoot(sub, "fp64", w.pix, beta=False)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
         frac = float((b32 != b64).sum()) / b64.numel()
-    return {"workload": "precision-study subtile: 2048^2 rays x 262144 stars",
-            "misbinned_fraction_fp32_bulk_vs_fp64": frac, "fp64_seconds": t64, "fp32_bulk_seconds": t32,
-            "speedup": t64 / t32}
+        c = torch.zeros((w.pix.NY, w.pix.NX), dtype=torch.int32, device="cuda")
+        t32, _ = median_seconds(torch, lambda: ctx.map(sub, w.pix, "fp32_bulk", counts=c), runs)
+        t64, _ = median_seconds(torch, lambda: ctx.map(sub, w.pix, "fp64", counts=c), runs)
+    inter = sub.n_rays * w.lens.n_stars
+    return {"workload": "precision-study subtile: 2048^2 rays x 262144 stars", "interactions": inter,
+            "misbinned_fraction_fp32_bulk_vs_fp64": frac, "misbinned_kind": "per ray",
+            "fp64_seconds": t64, "fp32_bulk_seconds": t32, "speedup": t64 / t32,
+            "fp64_interactions_per_s": inter / t64, "fp32_bulk_interactions_per_s": inter / t32}
 
 
-def split_section(torch, raysh, W):
+def split_section(torch, raysh, W, runs):
     """Many stars, few rays: 4194304 stars x 256^2 rays.  One pass per ray
     runs 16 workgroups; the split star sum spreads each ray's sum over
     workgroups (automatic part count)."""
@@ -159,18 +210,14 @@ def split_section(torch, raysh, W):
         for label, parts in (("split_auto", 0), ("one_pass", 1)):
             ctx.set_star_split(parts)
             counts = torch.zeros((w.pix.NY, w.pix.NX), dtype=torch.int32, device="cuda")
-            ctx.map(w.rays, w.pix, "fp64", counts=counts)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ctx.map(w.rays, w.pix, "fp64", counts=counts)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            out[label] = {"value": w.interactions / dt, "unit": "interactions/s", "seconds": dt}
+            dt, all_t = median_seconds(torch, lambda: ctx.map(w.rays, w.pix, "fp64", counts=counts), runs)
+            out[label] = {"value": w.interactions / dt, "unit": "interactions/s", "seconds": dt,
+                          "seconds_all": all_t}
     out["speedup"] = out["one_pass"]["seconds"] / out["split_auto"]["seconds"]
     return out
 
 
-def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup):
+def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup, runs):
     """FP64 with the far field of the star sum as local expansions, on the
     large configuration (time per map against the one-pass FP64 map, and the
     fraction of rays binned differently), and on the central 2048^2 rays of
@@ -191,17 +238,13 @@ def expansion_section(torch, raysh, W, w, fp64_seconds, steps, warmup):
     p = W.precision_study()
     sub = W.precision_subtile(p, 2048)
     with raysh.Context(p.lens) as ctx:
-        ctx.shoot(sub.block(0, 0, 256, 256), "fp64_expansion", p.pix, beta=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        ctx.shoot(sub.block(0, 0, 256, 256), "fp64_expansion", p.pix, beta=False)   # builds the star cells
         _, _, be = ctx.shoot(sub, "fp64_expansion", p.pix, beta=False)
-        torch.cuda.synchronize()
-        te = time.perf_counter() - t0
-        t0 = time.perf_counter()
         _, _, b64 = ctx.shoot(sub, "fp64", p.pix, beta=False)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
         frac = float((be != b64).sum()) / be.numel()
+        c = torch.zeros((p.pix.NY, p.pix.NX), dtype=torch.int32, device="cuda")
+        te, _ = median_seconds(torch, lambda: ctx.map(sub, p.pix, "fp64_expansion", counts=c), runs)
+        t64, _ = median_seconds(torch, lambda: ctx.map(sub, p.pix, "fp64", counts=c), runs)
     out["precision_study_subtile"] = {"workload": "2048^2 rays x 262144 stars", "seconds": te,
                                       "fp64_seconds": t64, "speedup_vs_fp64": t64 / te,
                                       "misbinned_fraction_vs_fp64": frac}
@@ -248,21 +291,35 @@ def light_curve_section(torch, raysh, W, steps, given_order=True):
         lc.append(c.elapsed_time(d))
         if given_order:
             lu.append(d.elapsed_time(e))
-    lc_ms = sum(lc) / len(lc)
+    med = lambda v: sorted(v)[len(v) // 2]   # noqa: E731
+    lc_ms = med(lc)
     samples = lw.n_tracks * lw.n_samples
     nbytes = samples * 8 + lw.n_tracks * (32 + 4) + mu.numel() * 8   # curves, end points + order, map
     achieved = nbytes / (lc_ms * 1e-3) / 1e9
     return {"workload": lw.name, "samples": samples,
-            "source_map_ms": sum(sm) / len(sm),
-            "track_order_ms": sum(so) / len(so),
+            "source_map_ms": med(sm),
+            "track_order_ms": med(so),
             "light_curve_kernel_ms": lc_ms,
-            "light_curve_kernel_ms_given_order": sum(lu) / len(lu) if lu else None,
+            "light_curve_kernel_ms_given_order": med(lu) if lu else None,
+            "timing": f"median of {len(lc)} runs (HIP events)",
             "samples_per_s": samples / (lc_ms * 1e-3),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "kernel": "light_curve_track_kernel",
                          "bytes_per_launch": nbytes,
                          "traffic": measured_traffic("light-curves-large 2^20 tracks x 256 samples, track order",
                                                      PROFILE_LC, "light_curve_track_kernel")}}
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(w, side):
@@ -274,6 +331,7 @@ def cpu_baseline(w, side):
     dt = time.perf_counter() - t0
     inter = blk.n_rays * w.lens.n_stars
     return {"value": inter / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "rays_per_s": blk.n_rays / dt,
             "sample": f"central {side}x{side} rays of the 8192^2 lattice x {w.lens.n_stars} stars "
                       f"({inter:.3e} interactions, {dt:.1f} s, single thread)"}
 
@@ -307,6 +365,7 @@ def cpu_parallel_baseline(w, side, procs):
     assert sum(done) == side
     inter = side * side * w.lens.n_stars
     return {"value": inter / dt, "unit": "interactions/s", "cores": procs, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"central {side}x{side} rays of the 8192^2 lattice x {w.lens.n_stars} stars in "
                       f"{procs} row bands, one process each ({inter:.3e} interactions, {dt:.1f} s)"}
 
@@ -347,6 +406,15 @@ def main():
     if args.tile32:
         cx, cy, st = (int(v) for v in args.tile32.split(","))
         ctx.set_tile("fp32_bulk", cx, cy, star_tile=st)
+    tuning = {}
+    for prec, given in (("fp64", args.tile), ("fp32_bulk", args.tile32)):
+        if given or args.no_tune:
+            tuning[prec] = {"tile": list(ctx.get_tile(prec)), "chosen_by": "given" if given else "library default"}
+            continue
+        print(f"# autotune {prec}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        t = ctx.autotune(w.rays, w.pix, prec, cache_path=args.tune_cache)
+        tuning[prec] = {"tile": list(t), "chosen_by": "raysh_autotune", "seconds": time.perf_counter() - t0}
     counts = torch.zeros((w.pix.NY, w.pix.NX), dtype=torch.int32, device="cuda")
 
     print(f"# fp64: {args.steps} steps after {args.warmup} warmup", file=sys.stderr, flush=True)
@@ -358,7 +426,7 @@ def main():
     tag = "plain-fp64-large tile %d,%d,%d,%d" % tile
 
     out = {
-        "metric": "ray-star interactions/s at 1 GPU (FP64 backward ray shooting, Algorithm 1)",
+        "metric": METRIC,
         "value": inter / (wall / args.steps),
         "unit": "interactions/s",
         "n_gpus": 1,
@@ -375,6 +443,7 @@ def main():
                    "kappa_star": w.lens.kappa_star, "kappa_c": w.lens.kappa_c,
                    "gamma": [w.lens.gamma1, w.lens.gamma2],
                    "tile_fp64": list(tile)},
+        "tuning": tuning,
         "rays_per_s": w.rays.n_rays / (wall / args.steps),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
@@ -386,16 +455,35 @@ def main():
         print("# fp32_bulk", file=sys.stderr, flush=True)
         c32 = torch.zeros_like(counts)
         wall32, kms32 = time_steps(torch, ctx, w, "fp32_bulk", c32, args.steps, args.warmup)
+        k32 = sum(kms32) / len(kms32)
+        ach32 = FLOP_PER_INTERACTION * inter / (k32 * 1e-3) / 1e12
+        tile32 = ctx.get_tile("fp32_bulk")
         m64 = ctx.map(w.rays, w.pix, "fp64")
         m32 = ctx.map(w.rays, w.pix, "fp32_bulk")
-        l1 = int((m64.long() - m32.long()).abs().sum())
-        dn = abs(int(m64.long().sum()) - int(m32.long().sum()))
+        lower = misbinned_lower_bound(m64, m32, w.rays.n_rays)
+        del m64, m32
+        per_ray = None
+        if not args.no_per_ray:
+            _, _, b64 = ctx.shoot(w.rays, "fp64", w.pix, beta=False)
+            _, _, b32 = ctx.shoot(w.rays, "fp32_bulk", w.pix, beta=False)
+            per_ray = float((b64 != b32).sum()) / w.rays.n_rays
+            del b64, b32
         out["fp32_bulk"] = {
             "value": inter / (wall32 / args.steps), "unit": "interactions/s",
-            "ms_per_step": 1e3 * wall32 / args.steps, "kernel_ms": sum(kms32) / len(kms32),
+            "rays_per_s": w.rays.n_rays / (wall32 / args.steps),
+            "ms_per_step": 1e3 * wall32 / args.steps, "kernel_ms": k32,
             "speedup_vs_fp64": wall / wall32,
-            "misbinned_fraction_lower_bound": 0.5 * (l1 + dn) / w.rays.n_rays,
-            "tile": list(ctx.get_tile("fp32_bulk"))}
+            "misbinned_fraction_vs_fp64": per_ray,
+            "misbinned_kind": "per ray, every ray of the 8192^2 lattice against the FP64 path's bins",
+            "misbinned_fraction_lower_bound_from_maps": lower,
+            "tile": list(tile32),
+            "roofline": {"bound": "alu", "achieved": ach32, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ach32 / FP32_VECTOR_PEAK_TFLOPS, "kernel": "shoot_fp32_kernel",
+                         "peak_note": "FP32 vector peak without packed instructions (packed FP32 is off in "
+                                      "this build); 157.3 TFLOP/s with them",
+                         "traffic": measured_traffic("plain-fp64-large tile32 %d,%d,%d,%d" % tile32,
+                                                     PROFILE_FP32, "shoot_fp32_kernel"),
+                         "kernel_ms": k32, "flop_per_launch": FLOP_PER_INTERACTION * inter}}
     ctx.close()
     del counts
     # end to end, as the paper times a map: context and star upload, one map,
@@ -416,20 +504,21 @@ def main():
     del m, host_map
     if not args.no_batch:
         print("# batch (64 sets)", file=sys.stderr, flush=True)
-        out["batch"] = batch_section(torch, raysh, W)
+        out["batch"] = batch_section(torch, raysh, W, args.runs, not args.no_tune, args.tune_cache)
     if not args.no_precision:
         print("# precision study", file=sys.stderr, flush=True)
-        out["precision_study"] = precision_section(torch, raysh, W)
+        out["precision_study"] = precision_section(torch, raysh, W, args.runs)
     if not args.no_split:
         print("# many stars, few rays (split star sum)", file=sys.stderr, flush=True)
-        out["split_star_sum"] = split_section(torch, raysh, W)
+        out["split_star_sum"] = split_section(torch, raysh, W, args.runs)
     if not args.no_expansion:
         print("# far-field expansion", file=sys.stderr, flush=True)
         out["fp64_expansion"] = expansion_section(torch, raysh, W, w, wall / args.steps, args.steps,
-                                                  args.warmup)
+                                                  args.warmup, args.runs)
     if not args.no_light_curves:
         print("# light curves", file=sys.stderr, flush=True)
-        out["light_curves"] = light_curve_section(torch, raysh, W, args.steps, not args.no_lc_given_order)
+        out["light_curves"] = light_curve_section(torch, raysh, W, max(args.steps, args.runs),
+                                                  not args.no_lc_given_order)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)

@@ -220,18 +220,39 @@ int raysh_get_tile(const raysh_ctx *ctx, int precision, int *cx, int *cy, int *s
 
 /*
  * raysh_autotune: time every launch shape compiled for `precision` on a
- * central sample of the ray block (about 2e10 / n_stars rays, at least
- * 256 x 256, at most the block) mapped into a scratch map, keep the fastest
- * in the context (as raysh_set_tile would) and return it through the
- * optional out-pointers.  cache_path (when NULL, the environment variable
+ * sample of the ray block mapped into a scratch map (one warm-up, then the
+ * median of three launches), keep the one with the shortest predicted time
+ * for the whole block in the context (as raysh_set_tile would) and return it
+ * through the optional out-pointers.  A shape's sample is a central part of
+ * the block made of whole tiles, in whole rounds of the workgroups the
+ * device holds at once (until about 1e11 ray-star interactions or the
+ * block's own rounds); its time per round, times the rounds the whole block
+ * takes, is the prediction.  cache_path (when NULL, the environment variable
  * RAYSH_AUTOTUNE_CACHE; no cache if both are unset) names a text file of
- * earlier choices keyed by GPU architecture, CU count, precision and
- * log2(n_stars): a hit skips the timing, a miss appends a line.
- * Synchronous.  Errors as raysh_map; ENOMEM if the scratch map cannot be
- * allocated.
+ * earlier choices keyed by GPU architecture, CU count, HIP runtime version,
+ * precision and log2(n_stars): a hit skips the timing, a miss appends a
+ * line.  Synchronous.  Errors as raysh_map; ENOMEM if the scratch map cannot
+ * be allocated.
  */
 int raysh_autotune(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix, int precision,
                    const char *cache_path, int *cx, int *cy, int *share, int *star_tile);
+
+/*
+ * raysh_autotune_batch: the launch shape of raysh_map_batch for these sets
+ * (arrays of length n_sets, as raysh_map_batch takes them): every shape
+ * compiled for `precision` is timed with the persistent batch kernel on a
+ * sample batch made of a central block of each set's rays (about an equal
+ * share of 1e11 ray-star interactions per set, sides in whole multiples of
+ * 128 rays so that no compiled tile is ragged in it, at most the block),
+ * mapped into scratch maps; the fastest is set in every
+ * context (raysh_map_batch uses the shape of sets[0]) and returned through
+ * the optional out-pointers.  The cache is that of raysh_autotune, keyed
+ * also by "batch" and by the mean star count of the sets.  Synchronous.
+ * Errors as raysh_map_batch; ENOMEM if the scratch maps cannot be
+ * allocated.  On error the contexts keep their shapes.
+ */
+int raysh_autotune_batch(raysh_ctx *const *sets, int n_sets, const raysh_rays *rays, const raysh_pixels *pix,
+                         int precision, const char *cache_path, int *cx, int *cy, int *share, int *star_tile);
 
 /*
  * raysh_shoot: per-ray results of Eq. (1) for one block of rays.

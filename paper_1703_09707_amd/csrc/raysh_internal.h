@@ -83,6 +83,9 @@ hipError_t launch_split_fp64(const ShootParams &p, const TileShape &shape, int p
 hipError_t launch_batch_fp32(const BatchArgs &b, const TileShape &shape, int blocks, hipStream_t s);
 int batch_fp64_blocks_per_cu(const TileShape &shape);
 int batch_fp32_blocks_per_cu(const TileShape &shape);
+// Workgroups of the one-shot kernels resident per compute unit.
+int shoot_fp64_blocks_per_cu(const TileShape &shape);
+int shoot_fp32_blocks_per_cu(const TileShape &shape);
 
 // Cells of the star field for the expansion mode: the star records sorted
 // by the cell of a regular grid (origin gx0, gy0, side h; cell c = j ncx + i),

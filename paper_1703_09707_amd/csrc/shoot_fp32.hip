@@ -165,6 +165,14 @@ int batch_blocks_per_cu() {
 }
 
 template <int CX, int CY, int S>
+int shoot_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, shoot_fp32_kernel<CX, CY, S>, kThreads, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+template <int CX, int CY, int S>
 hipError_t launch(const ShootParams &p, hipStream_t s) {
     const int64_t tiles_y = (p.ny + kLanesY * CY - 1) / (kLanesY * CY);
     ShootParams q = p;
@@ -217,6 +225,14 @@ hipError_t launch_batch_fp32(const BatchArgs &b, const TileShape &t, int blocks,
     RAYSH_FP32_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
     return hipErrorInvalidValue;
+}
+
+int shoot_fp32_blocks_per_cu(const TileShape &t) {
+#define RAYSH_CASE(CX, CY, S) \
+    if (t.cx == CX && t.cy == CY && t.star_tile == S) return shoot_blocks_per_cu<CX, CY, S>();
+    RAYSH_FP32_SHAPES(RAYSH_CASE)
+#undef RAYSH_CASE
+    return 1;
 }
 
 int batch_fp32_blocks_per_cu(const TileShape &t) {

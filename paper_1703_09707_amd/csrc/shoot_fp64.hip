@@ -431,6 +431,15 @@ int batch_blocks_per_cu() {
 }
 
 template <int CX, int CY, int SHARE, int NS>
+int shoot_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, shoot_fp64_kernel<CX, CY, SHARE, NS>, kThreads, 0) !=
+        hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+template <int CX, int CY, int SHARE, int NS>
 hipError_t launch(const ShootParams &p, hipStream_t s) {
     const int64_t tiles_y = (p.ny + kLanesY * CY - 1) / (kLanesY * CY);
     ShootParams q = p;
@@ -522,6 +531,15 @@ hipError_t launch_batch_fp64(const BatchArgs &b, const TileShape &t, int blocks,
     RAYSH_FP64_SHAPES(RAYSH_CASE)
 #undef RAYSH_CASE
     return hipErrorInvalidValue;
+}
+
+int shoot_fp64_blocks_per_cu(const TileShape &t) {
+#define RAYSH_CASE(CX, CY, S, NS)                                          \
+    if (t.cx == CX && t.cy == CY && t.share == S && t.star_tile == NS) \
+        return shoot_blocks_per_cu<CX, CY, S, NS>();
+    RAYSH_FP64_SHAPES(RAYSH_CASE)
+#undef RAYSH_CASE
+    return 1;
 }
 
 int batch_fp64_blocks_per_cu(const TileShape &t) {

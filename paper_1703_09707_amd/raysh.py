@@ -35,7 +35,8 @@ EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", 
            "raysh_set_expansion", "raysh_set_expansion_block", "raysh_set_expansion_cells",
            "raysh_expansion_order",
            "raysh_list_tiles",
-           "raysh_get_tile", "raysh_autotune", "raysh_shoot", "raysh_map", "raysh_map_batch",
+           "raysh_get_tile", "raysh_autotune", "raysh_autotune_batch", "raysh_shoot", "raysh_map",
+           "raysh_map_batch",
            "raysh_histogram_workspace", "raysh_log_mag_histogram",
            "raysh_source_map_shape", "raysh_source_map_workspace", "raysh_source_map", "raysh_light_curves",
            "raysh_track_order_workspace", "raysh_track_order",
@@ -145,6 +146,9 @@ def load():
         getattr(lib, name).restype = I
     lib.raysh_autotune.argtypes = [P, ctypes.POINTER(Rays), ctypes.POINTER(Pixels), I, ctypes.c_char_p] + \
         [ctypes.POINTER(I)] * 4
+    lib.raysh_autotune_batch.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(Rays), ctypes.POINTER(Pixels), I,
+                                         ctypes.c_char_p] + [ctypes.POINTER(I)] * 4
+    lib.raysh_autotune_batch.restype = I
     lib.raysh_shoot.argtypes = [P, ctypes.POINTER(Rays), I, P, P, ctypes.POINTER(Pixels), P]
     lib.raysh_map.argtypes = [P, ctypes.POINTER(Rays), ctypes.POINTER(Pixels), I, P,
                               ctypes.POINTER(ctypes.c_uint64)]
@@ -348,6 +352,20 @@ def map_batch(contexts, rays, pix, precision="fp64", counts=None):
     C = (ctypes.c_void_p * n)(*[c.data_ptr() for c in counts])
     check(load().raysh_map_batch(H, n, R, P, PRECISIONS[precision], C))
     return counts
+
+
+def autotune_batch(contexts, rays, pix, precision="fp64", cache_path=None):
+    """raysh_autotune_batch: time the compiled launch shapes with the batch
+    kernel on a sample of these sets, set the fastest in every context and
+    return it as (cx, cy, share, star_tile)."""
+    n = len(contexts)
+    R = (Rays * n)(*[rays_struct(r) for r in rays])
+    P = (Pixels * n)(*[pixels_struct(p) for p in pix])
+    H = (ctypes.c_void_p * n)(*[c.handle for c in contexts])
+    v = [ctypes.c_int() for _ in range(4)]
+    cp = cache_path.encode() if cache_path else None
+    check(load().raysh_autotune_batch(H, n, R, P, PRECISIONS[precision], cp, *[ctypes.byref(a) for a in v]))
+    return tuple(a.value for a in v)
 
 
 def source_map_shape(nx, ny, profile, size, px, py):

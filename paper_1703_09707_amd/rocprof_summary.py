@@ -144,6 +144,8 @@ def main(argv=None):
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="")
     ap.add_argument("--flop-per-launch", type=float, default=None)
+    ap.add_argument("--precision", choices=("f64", "f32"), default="f64",
+                    help="the VALU precision of the kernel's FLOP counters")
     ap.add_argument("--grid", type=int, default=None,
                     help="only dispatches of this grid size (threads) give the kernel's time")
     ap.add_argument("--pmc", nargs="*", default=[],
@@ -205,12 +207,14 @@ def main(argv=None):
                 scaled = avg[k] * factor if k.startswith("SQ_") else avg[k]
                 lines.append(f"  {k}: {avg[k]:.6e}  ->  {scaled:.6e}")
             avg = {k: (v * factor if k.startswith("SQ_") else v) for k, v in avg.items()}
-            f64 = 64 * (avg.get("SQ_INSTS_VALU_ADD_F64", 0) + avg.get("SQ_INSTS_VALU_MUL_F64", 0) +
-                        avg.get("SQ_INSTS_VALU_TRANS_F64", 0) + 2 * avg.get("SQ_INSTS_VALU_FMA_F64", 0))
-            lines.append(f"counter_flop_fp64_per_launch: {f64:.6e}")
+            P = a.precision.upper()
+            f64 = 64 * (avg.get(f"SQ_INSTS_VALU_ADD_{P}", 0) + avg.get(f"SQ_INSTS_VALU_MUL_{P}", 0) +
+                        avg.get(f"SQ_INSTS_VALU_TRANS_{P}", 0) + 2 * avg.get(f"SQ_INSTS_VALU_FMA_{P}", 0))
+            tag = "fp64" if a.precision == "f64" else "fp32"
+            lines.append(f"counter_flop_{tag}_per_launch: {f64:.6e}")
             if k_avg:
                 sec = k_avg * 1e-6
-                lines.append(f"counter_tflops_fp64: {f64 / sec / 1e12:.3f}")
+                lines.append(f"counter_tflops_{tag}: {f64 / sec / 1e12:.3f}")
                 grbm = per_instance_mean(a.valu, a.kernel, "GRBM_GUI_ACTIVE", a.grid)
                 if grbm:
                     clock = grbm / sec

@@ -2,11 +2,13 @@
  * A C caller of libraysh, with no Python or torch in the process: it reads a
  * lens and a ray lattice from argv/stdin-free constants, shoots one FP64
  * map (Algorithm 1 of arXiv:1703.09707) through the C ABI, and prints the
- * number of binned rays and a checksum of the map.  Device memory comes from
- * the HIP runtime directly.  Exit status: 0 on success, 2 when raysh_init
- * reports an error (for example when no GPU is present), 1 otherwise.
+ * number of binned rays and a checksum of the map; with a third argument it
+ * also writes the map there (256 x 256 int32, row-major, native byte order).
+ * Device memory comes from the HIP runtime directly.  Exit status: 0 on
+ * success, 2 when raysh_init reports an error (for example when no GPU is
+ * present), 1 otherwise.
  *
- * Usage: map_from_c <n_stars> <seed>
+ * Usage: map_from_c <n_stars> <seed> [map_file]
  */
 #include <stdint.h>
 #include <stdio.h>
@@ -28,8 +30,8 @@ static uint64_t next(uint64_t *s) {
 static double unit(uint64_t *s) { return (double)(next(s) >> 11) * (1.0 / 9007199254740992.0); }
 
 int main(int argc, char **argv) {
-    if (argc != 3) {
-        fprintf(stderr, "usage: %s <n_stars> <seed>\n", argv[0]);
+    if (argc != 3 && argc != 4) {
+        fprintf(stderr, "usage: %s <n_stars> <seed> [map_file]\n", argv[0]);
         return 1;
     }
     const int64_t n = atoll(argv[1]);
@@ -79,6 +81,13 @@ int main(int argc, char **argv) {
     }
     printf("binned %llu sum %llu weighted %llu\n", (unsigned long long)binned, (unsigned long long)sum,
            (unsigned long long)weighted);
+    if (argc == 4) {
+        FILE *f = fopen(argv[3], "wb");
+        if (!f || fwrite(host, sizeof(int32_t), 256 * 256, f) != 256 * 256 || fclose(f) != 0) {
+            printf("cannot write %s\n", argv[3]);
+            return 1;
+        }
+    }
     free(host);
     (void)hipFree(counts);
     return raysh_free(ctx) == RAYSH_OK ? 0 : 1;

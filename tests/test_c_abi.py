@@ -1,6 +1,7 @@
 """The C ABI from a C program (no Python or torch in its process): it builds
 against include/raysh.h and links libraysh.so; without a GPU raysh_init
-reports an error cleanly, with one the map equals the Python binding's."""
+reports an error cleanly, with one its map equals the Python binding's,
+pixel by pixel."""
 import os
 import shutil
 import subprocess
@@ -61,12 +62,13 @@ def test_c_program_builds_and_reports_errors_without_gpu(program):
 
 
 @pytest.mark.gpu
-def test_c_program_map_equals_python_binding(program):
+def test_c_program_map_equals_python_binding(program, tmp_path):
     import torch
     from paper_1703_09707_amd import raysh as R
     if not torch.cuda.is_available():
         pytest.fail("GPU tests need a ROCm GPU")
-    r = subprocess.run([program, "300", "7"], capture_output=True, text=True, timeout=120)
+    map_file = str(tmp_path / "map.i32")
+    r = subprocess.run([program, "300", "7", map_file], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, (r.stdout, r.stderr)
     _, binned, _, total, _, weighted = r.stdout.split()
     x, y, m = splitmix_stars(300, 7)
@@ -74,6 +76,8 @@ def test_c_program_map_equals_python_binding(program):
     pix = (-5.0, -5.0, 10.0 / 256, 10.0 / 256, 256, 256)
     with R.Context((0.1, 0.2, -0.05, x, y, m)) as ctx:
         counts, nb = ctx.map(rays, pix, "fp64", n_binned=True)
+    from_c = np.fromfile(map_file, dtype=np.int32).reshape(256, 256)
+    np.testing.assert_array_equal(from_c, counts.cpu().numpy())
     c = counts.cpu().numpy().astype(np.uint64).ravel()
     assert int(binned) == nb == int(c.sum()) == int(total)
     assert int(weighted) == int((c * np.arange(1, c.size + 1, dtype=np.uint64)).sum())

@@ -466,6 +466,33 @@ def test_autotune_picks_compiled_shape_and_caches(torch, small, tmp_path):
     assert len([l for l in open(cache).read().split("\n") if l.strip()]) == 2
 
 
+def test_autotune_batch_picks_compiled_shape_and_caches(torch, small_batch, tmp_path):
+    """raysh_autotune_batch times the shapes with the batch kernel, sets the
+    fastest in every context, and the batch then equals its single launches
+    with that shape; a second call is answered from the cache."""
+    cache = str(tmp_path / "tune_batch.txt")
+    ctxs = [R.Context(w.lens) for w in small_batch]
+    try:
+        rays, pix = [w.rays for w in small_batch], [w.pix for w in small_batch]
+        t64 = R.autotune_batch(ctxs, rays, pix, "fp64", cache_path=cache)
+        assert tuple(t64) in FP64_SHAPES and all(c.get_tile("fp64") == t64 for c in ctxs)
+        maps = R.map_batch(ctxs, rays, pix, "fp64")
+        for c, w, m in zip(ctxs, small_batch, maps):
+            assert torch.equal(m, c.map(w.rays, w.pix, "fp64"))
+        t32 = R.autotune_batch(ctxs, rays, pix, "fp32_bulk", cache_path=cache)
+        assert (t32[0], t32[1], t32[3]) in FP32_SHAPES and t32[2] == 0
+        lines = [l for l in open(cache).read().split("\n") if l.strip()]
+        assert len(lines) == 2 and all(" batch " in l for l in lines)
+        for c in ctxs:
+            c.set_tile("fp64", 2, 2, share=2)
+        assert R.autotune_batch(ctxs, rays, pix, "fp64", cache_path=cache) == t64   # a cache hit
+        assert all(c.get_tile("fp64") == t64 for c in ctxs)
+        assert len([l for l in open(cache).read().split("\n") if l.strip()]) == 2
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 # ----------------------------------------------------------------- full sizes, maximum sizes
 def test_batch_full_size_equals_single_launches(torch):
     """The 64-set workload at full size (4096^2 rays per set, N* 511..43689):
