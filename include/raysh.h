@@ -286,6 +286,24 @@ int raysh_map(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix,
               int precision, int32_t *counts, uint64_t *n_binned);
 
 /*
+ * raysh_map_split_noalloc: raysh_map in RAYSH_FP64 with each ray's star sum
+ * split over `parts` contiguous star ranges (as raysh_set_star_split; 0 =
+ * automatic, 1 = one pass), for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  It allocates nothing and never synchronizes: the partial
+ * sums (parts * nx * ny * 16 bytes) go to a static device array of 64 MiB
+ * that the library holds on each device it runs on until the process ends
+ * (its address is resolved by raysh_init).  Every call on a device shares
+ * that array, so calls that overlap on one device race; each call writes
+ * every partial sum it reads.  The map is accumulated, as in raysh_map, and
+ * equals raysh_map's for the same split, bit for bit.
+ * Errors as raysh_map; EINVAL when parts is outside [0, 65536]; EOVERFLOW
+ * when the partial sums exceed 64 MiB (nothing is enqueued).
+ */
+int raysh_map_split_noalloc(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix, int parts,
+                            int32_t *counts);
+
+/*
  * raysh_map_batch: raysh_map for n_sets independent lenses in one launch
  * (Sec. 2.2 mentions grids of independent simulations over lens parameters).
  * sets[s] is a context (all on one device; the stream of sets[0] is used),

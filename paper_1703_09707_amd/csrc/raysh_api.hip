@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <vector>
 
 #include "raysh_ctx.h"
@@ -26,9 +27,10 @@ constexpr size_t kMaxSplitBytes = size_t(2) << 30;   // automatic split-K worksp
 constexpr int64_t kCellAutoStars = 65536;             // star cells by default from this many stars on
 constexpr int kMinStarsPerPart = 64;
 
-// Parts of the FP64 star sum for this call (1 = one pass).
-int split_parts(const raysh_ctx *c, const ShootParams &p) {
-    if (c->star_parts >= 1) return c->star_parts;   // as set (1 = one pass)
+// Parts of the FP64 star sum for a call (1 = one pass): `want` >= 1 as
+// given, 0 automatic with a workspace of at most cap_bytes.
+int split_parts(const raysh_ctx *c, const ShootParams &p, int want, size_t cap_bytes) {
+    if (want >= 1) return want;   // as set (1 = one pass)
     // automatic: enough (tile, part) workgroups to fill the GPU several times
     if (c->n_stars < 2 * kMinStarsPerPart) return 1;
     const int64_t n_rays = p.nx * p.ny;
@@ -38,14 +40,41 @@ int split_parts(const raysh_ctx *c, const ShootParams &p) {
     const int64_t want_blocks = (int64_t)std::max(c->n_cu, 1) * 8;   // several waves of workgroups
     int64_t parts = (want_blocks + tiles - 1) / tiles;
     parts = std::min<int64_t>(parts, c->n_stars / kMinStarsPerPart);
-    parts = std::min<int64_t>(parts, (int64_t)(kMaxSplitBytes / (16 * (size_t)n_rays)));
+    parts = std::min<int64_t>(parts, (int64_t)(cap_bytes / (16 * (size_t)n_rays)));
     return (int)std::max<int64_t>(parts, 1);
+}
+
+// Allocation-free FP64 map: the split star sum's partial sums go to this
+// file-scope device array instead of a context workspace.  Each device
+// holds its own copy until the process ends; its address is resolved once
+// per device (bind_scratch, from raysh_init) and only that address is used
+// on the host side.  Calls that overlap on one device share it and race.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: the device address of `scratch` on it, resolved
+// on the first call for the device.
+hipError_t bind_scratch(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 int launch(raysh_ctx *c, const ShootParams &p, int precision, const char *what) {
     hipError_t e;
     if (precision == RAYSH_FP64) {
-        const int parts = split_parts(c, p);
+        const int parts = split_parts(c, p, c->star_parts, kMaxSplitBytes);
         if (parts > 1) {
             const size_t need = (size_t)parts * (size_t)(p.nx * p.ny) * sizeof(double2);
             if (need > c->partial_bytes) {
@@ -289,6 +318,9 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
 
     DeviceGuard g(device);
     if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", device);
+    void *static_scratch = nullptr;
+    e = bind_scratch(device, &static_scratch);
+    if (e != hipSuccess) return hip_error(e, "raysh_init: static scratch of raysh_map_split_noalloc");
     raysh_ctx *c = new raysh_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -471,6 +503,38 @@ int raysh_map(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix, i
         if (e != hipSuccess) return hip_error(e, "raysh_map");
         *n_binned = *ctx->h_counter;
     }
+    return set_ok();
+}
+
+int raysh_map_split_noalloc(raysh_ctx *ctx, const raysh_rays *rays, const raysh_pixels *pix, int parts,
+                            int32_t *counts) {
+    if (int r = validate_rays(rays)) return r;
+    if (int r = validate_pixels(pix)) return r;
+    if (!counts) return set_error(RAYSH_EINVAL, "counts is NULL");
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    if (parts < 0 || parts > 65536) return set_error(RAYSH_EINVAL, "star split %d outside [0, 65536]", parts);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    const size_t map_bytes = (size_t)pix->nx * (size_t)pix->ny * 4;
+    if (int r = validate_device_ptr(counts, map_bytes, ctx->device, "counts")) return r;
+    const int64_t n = rays->nx * rays->ny;
+    if (n == 0) return set_ok();
+    ShootParams p{};
+    fill_shoot_params(p, ctx, rays, pix);
+    p.counts = counts;
+    const int use = split_parts(ctx, p, parts, kStaticScratchBytes);
+    const size_t need = (size_t)use * (size_t)n * sizeof(double2);
+    if (use > 1 && need > kStaticScratchBytes)
+        return set_error(RAYSH_EOVERFLOW,
+                         "raysh_map_split_noalloc: %d parts of %lld rays need %zu bytes of partial sums, "
+                         "beyond its static scratch of %zu bytes",
+                         use, (long long)n, need, kStaticScratchBytes);
+    void *ptr = nullptr;
+    hipError_t e = bind_scratch(ctx->device, &ptr);   // resolved by raysh_init; no allocation here
+    if (e != hipSuccess) return hip_error(e, "raysh_map_split_noalloc");
+    e = use > 1 ? raysh::launch_split_fp64(p, ctx->shape[0], use, static_cast<double2 *>(ptr), ctx->stream)
+                : raysh::launch_shoot_fp64(p, ctx->shape[0], ctx->stream);
+    if (e != hipSuccess) return hip_error(e, "raysh_map_split_noalloc");
     return set_ok();
 }
 

@@ -35,7 +35,7 @@ EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", 
            "raysh_set_expansion", "raysh_set_expansion_block", "raysh_set_expansion_cells",
            "raysh_expansion_order",
            "raysh_list_tiles",
-           "raysh_get_tile", "raysh_autotune", "raysh_autotune_batch", "raysh_shoot", "raysh_map",
+           "raysh_get_tile", "raysh_autotune", "raysh_autotune_batch", "raysh_shoot", "raysh_map", "raysh_map_split_noalloc",
            "raysh_map_batch",
            "raysh_histogram_workspace", "raysh_log_mag_histogram",
            "raysh_source_map_shape", "raysh_source_map_workspace", "raysh_source_map", "raysh_light_curves",
@@ -152,6 +152,8 @@ def load():
     lib.raysh_shoot.argtypes = [P, ctypes.POINTER(Rays), I, P, P, ctypes.POINTER(Pixels), P]
     lib.raysh_map.argtypes = [P, ctypes.POINTER(Rays), ctypes.POINTER(Pixels), I, P,
                               ctypes.POINTER(ctypes.c_uint64)]
+    lib.raysh_map_split_noalloc.argtypes = [P, ctypes.POINTER(Rays), ctypes.POINTER(Pixels), I, P]
+    lib.raysh_map_split_noalloc.restype = I
     lib.raysh_map_batch.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(Rays),
                                     ctypes.POINTER(Pixels), I, ctypes.POINTER(P)]
     lib.raysh_sync.argtypes = [P]
@@ -299,6 +301,18 @@ class Context:
         check(load().raysh_map(self.handle, ctypes.byref(r), ctypes.byref(p), PRECISIONS[precision],
                                _ptr(counts), ctypes.byref(nb) if n_binned else None))
         return (counts, int(nb.value)) if n_binned else counts
+
+    def map_split_noalloc(self, rays, pix, parts, counts):
+        """raysh_map_split_noalloc: FP64 counts added into the caller's
+        `counts`, the star sum split in `parts` (0 = automatic), with the
+        partial sums in the library's static device array (no allocation)."""
+        r = rays_struct(rays)
+        p = pixels_struct(pix)
+        if counts.dtype.itemsize != 4 or not counts.is_contiguous() or counts.numel() != p.nx * p.ny:
+            raise ValueError("counts must be a contiguous int32 tensor of ny*nx elements")
+        check(load().raysh_map_split_noalloc(self.handle, ctypes.byref(r), ctypes.byref(p), int(parts),
+                                             _ptr(counts)))
+        return counts
 
     def sync(self):
         check(load().raysh_sync(self.handle))
