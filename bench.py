@@ -75,6 +75,7 @@ def parse():
                          "every dispatch of the map kernels at full size is a map)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, always timed)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate section")
+    ap.add_argument("--surrogate-steps", type=int, default=20000, help="training steps of the surrogate section")
     ap.add_argument("--runs", type=int, default=5, help="runs per secondary timing (median reported)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer 3 times (the reference kernel for "
@@ -310,6 +311,27 @@ def light_curve_section(torch, raysh, W, steps, given_order=True):
                                                      PROFILE_LC, "light_curve_track_kernel")}}
 
 
+def surrogate_section(steps):
+    """The learned part at its full size: 4096 shooter-generated 512^2 maps
+    (4096^2 rays each, FP64 with the far field expanded) over sampled
+    (kappa, gamma, kappa_*/kappa), four Gaussian sources per map; the
+    network trained on them by the library's kernels; judged on 256
+    held-out sets against the mean of four star-field realisations each;
+    out-of-domain queries answered by the plain FP64 shooter."""
+    from paper_1703_09707_amd import surrogate as S
+
+    def log(msg):
+        if not msg.startswith("  "):
+            print(msg, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    res = S.run(steps=steps, log=log)
+    res["seconds_total"] = time.perf_counter() - t0
+    res["workload"] = ("surrogate: 4096 training maps of 512^2 pixels (4096^2 rays each), 4 Gaussian sources "
+                       "per map, 3-layer MLP (width 256, BF16 weights, FP32 accumulation), 64-bin "
+                       "log-magnification histograms, 256 held-out sets")
+    return res
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo)."""
     try:
@@ -519,6 +541,9 @@ def main():
         print("# light curves", file=sys.stderr, flush=True)
         out["light_curves"] = light_curve_section(torch, raysh, W, max(args.steps, args.runs),
                                                   not args.no_lc_given_order)
+    if not args.no_surrogate:
+        print("# learned surrogate", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_section(args.surrogate_steps)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)

@@ -12,6 +12,14 @@ network's predictions, with the realisation-noise floor (two star fields at
 the same parameters) and with a no-network baseline (the nearest training
 example in standardised feature space).
 
+Queries go through ``Surrogate``: a query whose standardised features lie
+inside the training data's box and near a training example is answered by
+the network; any other query is answered by shooting its map and taking its
+histogram (the plain shooter as fallback), so the surrogate never
+extrapolates.  The held-out judge compares with the mean histogram of
+several star-field realisations per parameter set, so that it measures the
+network's error and not the scatter of one realisation.
+
 Every numerical step runs in libraysh's kernels (raysh_map_batch, or
 raysh_map per set for the expansion mode, raysh_log_mag_histogram,
 raysh_mlp_*); this module marshals arguments, draws parameters and loops
@@ -276,6 +284,72 @@ def train(data: Dataset, steps=3000, batch=256, lr=2e-3, hidden=256, seed=0, dev
     return net, std, hist
 
 
+# ----------------------------------------------------------------- one parameter set, shot
+@dataclasses.dataclass
+class ShooterConfig:
+    """How the fallback (and the data) shoot a parameter set: a square
+    lattice of rays_per_side^2 rays over the preimage box of a window of
+    `window` x `window` Einstein angles binned into npix^2 pixels."""
+    rays_per_side: int = 4096
+    npix: int = 512
+    window: float = 10.0
+    precision: str = "fp64"
+    max_stars: int = 1 << 21
+
+
+def lens_for(kappa, gamma, f, window, rng, max_stars=1 << 21):
+    """The lens of one parameter set, drawn as the data are (workloads.
+    draw_batch_params): kappa_* = f kappa, kappa_c = kappa - kappa_*,
+    gamma2 = 0, a disk of radius 1.2 x the preimage box's half diagonal
+    holding N* = round(kappa_* R^2 / <m>) Salpeter stars.  Returns
+    (lens tuple, hx, hy).  ValueError for parameters the shooter cannot
+    answer: not finite, kappa outside [0, 2), f outside [0, 1], gamma < 0,
+    a macro lens within 1e-3 of critical (|det A| < 1e-3), or more than
+    max_stars stars."""
+    vals = (kappa, gamma, f)
+    if not all(math.isfinite(v) for v in vals):
+        raise ValueError(f"parameters not finite: {vals}")
+    if not (0.0 <= kappa < 2.0 and 0.0 <= f <= 1.0 and gamma >= 0.0):
+        raise ValueError(f"parameters outside the shooter's range: kappa {kappa}, gamma {gamma}, f {f}")
+    det = (1 - kappa) ** 2 - gamma ** 2
+    if abs(det) < 1e-3:
+        raise ValueError(f"macro lens too close to critical: |det A| = {abs(det):.2e}")
+    hx, hy = W.preimage_half_widths(kappa, gamma, 0.0, window / 2, window / 2)
+    radius = 1.2 * math.hypot(hx, hy)
+    ks = f * kappa
+    n = int(round(ks * radius ** 2 / W.salpeter_mean()))
+    if n > max_stars:
+        raise ValueError(f"{n} stars exceed the fallback's limit of {max_stars}")
+    m = W.salpeter_masses(n, rng)
+    x, y, _ = W.star_field(m, ks, rng) if n > 0 else (np.zeros(0), np.zeros(0), None)
+    return (kappa - ks, gamma, 0.0, x, y, m), hx, hy
+
+
+def shoot_histograms(features, cfg: ShooterConfig, seed, device=0):
+    """The shooter's histograms for rows of raw features (kappa, gamma, f,
+    log10 sigma): one map per row (star field seeded by seed + row), seen by
+    a Gaussian source of width sigma.  ValueError for a row the shooter
+    cannot answer (see lens_for; also a source too large for the map)."""
+    torch = _torch()
+    feats = np.atleast_2d(np.asarray(features, np.float64))
+    pix = W.centred_window(cfg.window, cfg.npix)
+    hist = Histogrammer(cfg.npix, cfg.npix, device)
+    out = np.empty((len(feats), N_BINS), np.float32)
+    for r, (kappa, gamma, f, lsig) in enumerate(feats):
+        sigma = 10.0 ** lsig
+        if not (math.isfinite(sigma) and 0.0 < 3.0 * sigma < 0.5 * cfg.window):
+            raise ValueError(f"source width {sigma} does not fit the {cfg.window} x {cfg.window} window")
+        rng = np.random.Generator(np.random.PCG64(seed + r))
+        lens, hx, hy = lens_for(kappa, gamma, f, cfg.window, rng, cfg.max_stars)
+        grid = W.centred_rays(hx, hy, cfg.rays_per_side, cfg.rays_per_side)
+        with R.Context(lens, device=device) as ctx:
+            counts = ctx.map(grid, pix, cfg.precision)
+        norm = (grid.dx * grid.dy) / (pix.Px * pix.Py)
+        _, h = hist(counts, norm, sigma, pix.Px, pix.Py, W.mean_magnification(kappa, gamma, 0.0))
+        out[r] = h.cpu().numpy()
+    return out
+
+
 def predict(net: MLP, std: Standardiser, features):
     torch = _torch()
     x = torch.from_numpy(std(np.asarray(features, np.float32))).to(f"cuda:{net.device}")
@@ -285,20 +359,164 @@ def predict(net: MLP, std: Standardiser, features):
     return torch.cat(out).cpu().numpy()
 
 
-def evaluate(net, std, train_data: Dataset, test_data: Dataset, noise_data: Dataset | None = None):
+def evaluate(net, std, train_data: Dataset, test_data: Dataset, noise_data: Dataset | None = None,
+             realisations=()):
     """Held-out L1 of the network, of the nearest-neighbour baseline and of
-    the training-mean histogram; with noise_data (the test sets shot again
-    with other star fields, same sources) also the realisation-noise floor."""
+    the training-mean histogram against the held-out histograms.
+
+    test_data holds one star-field realisation per held-out set; the
+    `realisations` (more Datasets of the same sets and sources, other star
+    fields) join it in the target, which is then the mean histogram of all
+    of them (so the judge measures the network's error rather than the
+    scatter of one realisation).  noise_data, one more independent
+    realisation, gives the realisation-noise floor: its L1 to the same
+    target."""
+    runs = [test_data, *realisations]
+    for d in runs[1:]:
+        assert np.array_equal(d.features, test_data.features), "realisations of other sets or sources"
+    target = np.mean([d.hist.astype(np.float64) for d in runs], axis=0)
     pred = predict(net, std, test_data.features)
     nn = nearest_neighbour(std(train_data.features), train_data.hist, std(test_data.features))
     mean = np.broadcast_to(train_data.hist.mean(axis=0), test_data.hist.shape)
-    out = {"l1_network": float(l1(pred, test_data.hist).mean()),
-           "l1_nearest_neighbour": float(l1(nn, test_data.hist).mean()),
-           "l1_training_mean": float(l1(mean, test_data.hist).mean()),
+    out = {"l1_network": float(l1(pred, target).mean()),
+           "l1_nearest_neighbour": float(l1(nn, target).mean()),
+           "l1_training_mean": float(l1(mean, target).mean()),
+           "realisations_per_target": len(runs),
            "n_test": int(len(test_data.hist))}
     if noise_data is not None:
-        out["l1_noise_floor"] = float(l1(noise_data.hist, test_data.hist).mean())
+        out["l1_noise_floor"] = float(l1(noise_data.hist, target).mean())
     return out, pred
+
+
+@dataclasses.dataclass
+class Domain:
+    """Where the network may answer: standardised features inside the
+    training data's box and no farther from a training example than
+    `radius` (twice the 99th percentile of the training examples' own
+    nearest-neighbour distances)."""
+    lo: np.ndarray
+    hi: np.ndarray
+    radius: float
+    points: np.ndarray
+
+    @classmethod
+    def fit(cls, xs):
+        xs = np.asarray(xs, np.float64)
+        d = _nn_distances(xs, xs, exclude_self=True)
+        return cls(xs.min(axis=0), xs.max(axis=0), 2.0 * float(np.quantile(d, 0.99)), xs)
+
+    def contains(self, xs):
+        xs = np.atleast_2d(np.asarray(xs, np.float64))
+        inside = np.all((xs >= self.lo) & (xs <= self.hi), axis=1) & np.all(np.isfinite(xs), axis=1)
+        near = np.zeros(len(xs), bool)
+        if inside.any():
+            near[inside] = _nn_distances(xs[inside], self.points) <= self.radius
+        return inside & near
+
+
+def _nn_distances(q, pts, exclude_self=False, chunk=2048):
+    """Distance from each row of q to its nearest row of pts."""
+    out = np.empty(len(q))
+    for i in range(0, len(q), chunk):
+        d = ((q[i:i + chunk, None, :] - pts[None, :, :]) ** 2).sum(-1)
+        if exclude_self:
+            d[np.arange(d.shape[0]), np.arange(i, i + d.shape[0])] = np.inf
+        out[i:i + chunk] = np.sqrt(d.min(axis=1))
+    return out
+
+
+class Surrogate:
+    """The trained network with its domain, and the shooter behind it.
+
+    query(features) answers rows inside the domain with the network and
+    every other row by shooting it (shoot_histograms with `cfg`): the plain
+    shooter is the fallback.  Returns (histograms [n, 64], source per row:
+    "network" or "shooter")."""
+
+    def __init__(self, net: MLP, std: Standardiser, train_data: Dataset, cfg: ShooterConfig | None = None,
+                 seed=W.BASE_SEED + 9):
+        self.net, self.std, self.cfg, self.seed = net, std, cfg or ShooterConfig(), seed
+        self.domain = Domain.fit(std(train_data.features))
+
+    def in_domain(self, features):
+        return self.domain.contains(self.std(np.atleast_2d(np.asarray(features, np.float32))))
+
+    def query(self, features):
+        feats = np.atleast_2d(np.asarray(features, np.float64))
+        ok = self.in_domain(feats)
+        out = np.empty((len(feats), N_BINS), np.float32)
+        if ok.any():
+            out[ok] = predict(self.net, self.std, feats[ok])
+        if (~ok).any():
+            out[~ok] = shoot_histograms(feats[~ok], self.cfg, self.seed, self.net.device)
+        return out, np.where(ok, "network", "shooter")
+
+
+def run(train_sets=4096, test_sets=256, rays=4096, npix=512, sigmas=4, steps=20000, batch=256, lr=2e-3,
+        precision="fp64_expansion", seed=W.BASE_SEED + 4, realisations=4, log=None):
+    """The whole learned part at a given size: shoot the training maps and
+    the held-out maps (`realisations` star fields per held-out set, plus one
+    more for the noise floor), train, judge, time the network against the
+    shooter and answer out-of-domain queries through the fallback.  Returns
+    a dict of results."""
+    torch = _torch()
+    log = log or (lambda msg: None)
+    kw = dict(rays_per_side=rays, npix=npix, sigmas_per_map=sigmas, precision=precision, log=log)
+    t0 = time.perf_counter()
+    log("# training maps")
+    train_data = generate(train_sets, seed, **kw)
+    log("# held-out maps")
+    test_rng = np.random.Generator(np.random.PCG64(seed + 1))
+    test_params, _ = W.draw_batch_params(test_rng, test_sets)
+    runs = [generate(test_sets, seed + 1, params=test_params, star_seed_offset=500000 * k, **kw)
+            for k in range(realisations)]
+    log("# held-out parameters again, another star field (noise floor)")
+    noise_data = generate(test_sets, seed + 1, params=test_params, star_seed_offset=500000 * realisations, **kw)
+    t_data = time.perf_counter() - t0
+    log("# training")
+    t1 = time.perf_counter()
+    net, std, hist = train(train_data, steps=steps, batch=batch, lr=lr, log=log)
+    t_train = time.perf_counter() - t1
+    res, pred = evaluate(net, std, train_data, runs[0], noise_data, realisations=runs[1:])
+    single, _ = evaluate(net, std, train_data, runs[0])
+    x = torch.from_numpy(std(runs[0].features)).cuda()
+    chunks = [x[i:i + net.max_batch].contiguous() for i in range(0, x.shape[0], net.max_batch)]
+    for c in chunks:
+        net.forward(c)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(20):
+        for c in chunks:
+            net.forward(c)
+    torch.cuda.synchronize()
+    t_pred = (time.perf_counter() - t2) / 20
+    # the fallback: queries outside the training domain are shot
+    sur = Surrogate(net, std, train_data, ShooterConfig(rays_per_side=rays, npix=npix, precision="fp64"))
+    inside = sur.in_domain(runs[0].features)
+    outside = np.array([[0.9, 0.05, 0.5, -1.0], [0.3, 0.75, 0.4, -0.5], [0.5, 0.3, 0.6, 0.1]])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    _, src = sur.query(outside)
+    torch.cuda.synchronize()
+    t_fb = (time.perf_counter() - t3) / len(outside)
+    res.update({
+        "l1_against_one_realisation": {k: single[k] for k in ("l1_network", "l1_nearest_neighbour",
+                                                               "l1_training_mean")},
+        "train_examples": int(len(train_data.hist)), "train_sets": train_sets, "test_sets": test_sets,
+        "rays_per_map": rays ** 2, "map": [npix, npix], "sigmas_per_map": sigmas,
+        "precision": precision, "steps": steps, "batch": batch,
+        "loss_first_last": [hist[0][1], hist[-1][1]],
+        "seconds_data": t_data, "seconds_shooting": train_data.seconds_shooting + sum(
+            d.seconds_shooting for d in runs) + noise_data.seconds_shooting, "seconds_train": t_train,
+        "interactions": train_data.interactions + sum(d.interactions for d in runs) + noise_data.interactions,
+        "predict_us_per_example": 1e6 * t_pred / len(runs[0].hist),
+        "shoot_ms_per_map": 1e3 * runs[0].seconds_shooting / test_sets,
+        "held_out_in_domain": float(inside.mean()),
+        "fallback": {"queries": outside.tolist(), "answered_by": src.tolist(),
+                     "ms_per_query": 1e3 * t_fb, "precision": "fp64"},
+    })
+    net.close()
+    return res
 
 
 def main(argv=None):
@@ -318,6 +536,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--precision", default="fp64_expansion",
                     help="how the maps are shot: fp64_expansion, fp32_bulk or fp64")
+    ap.add_argument("--realisations", type=int, default=4,
+                    help="star fields per held-out set averaged into the judge's target")
     ap.add_argument("--seed", type=int, default=W.BASE_SEED + 4)
     ap.add_argument("--out", default=None, help="write the JSON result here too")
     a = ap.parse_args(argv)
@@ -325,51 +545,13 @@ def main(argv=None):
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
-    kw = dict(rays_per_side=a.rays, npix=a.npix, sigmas_per_map=a.sigmas, precision=a.precision, log=log)
-    t0 = time.perf_counter()
-    log("# training maps")
-    train_data = generate(a.train_sets, a.seed, **kw)
-    log("# held-out maps")
-    test_rng = np.random.Generator(np.random.PCG64(a.seed + 1))
-    test_params, _ = W.draw_batch_params(test_rng, a.test_sets)
-    test_data = generate(a.test_sets, a.seed + 1, params=test_params, **kw)
-    log("# held-out parameters again, other star fields (noise floor)")
-    noise_data = generate(a.test_sets, a.seed + 1, params=test_params, star_seed_offset=500000, **kw)
-    t_data = time.perf_counter() - t0
-    log("# training")
-    t1 = time.perf_counter()
-    net, std, hist = train(train_data, steps=a.steps, batch=a.batch, lr=a.lr, log=log)
-    t_train = time.perf_counter() - t1
-    res, pred = evaluate(net, std, train_data, test_data, noise_data)
-    torch = _torch()
-    x = torch.from_numpy(std(test_data.features)).cuda()
-    chunks = [x[i:i + net.max_batch].contiguous() for i in range(0, x.shape[0], net.max_batch)]
-    for c in chunks:
-        net.forward(c)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(20):
-        for c in chunks:
-            net.forward(c)
-    torch.cuda.synchronize()
-    t_pred = (time.perf_counter() - t2) / 20
-    res.update({
-        "train_examples": int(len(train_data.hist)), "train_sets": a.train_sets, "test_sets": a.test_sets,
-        "rays_per_map": a.rays ** 2, "map": [a.npix, a.npix], "sigmas_per_map": a.sigmas,
-        "precision": a.precision, "steps": a.steps, "batch": a.batch,
-        "loss_first_last": [hist[0][1], hist[-1][1]],
-        "seconds_data": t_data, "seconds_shooting": train_data.seconds_shooting + test_data.seconds_shooting
-        + noise_data.seconds_shooting, "seconds_train": t_train,
-        "interactions": train_data.interactions + test_data.interactions + noise_data.interactions,
-        "predict_us_per_example": 1e6 * t_pred / len(test_data.hist),
-        "shoot_ms_per_map": 1e3 * test_data.seconds_shooting / a.test_sets,
-    })
+    res = run(a.train_sets, a.test_sets, a.rays, a.npix, a.sigmas, a.steps, a.batch, a.lr, a.precision, a.seed,
+              a.realisations, log)
     line = json.dumps(res)
     print(line, flush=True)
     if a.out:
         with open(a.out, "w") as f:
             f.write(line + "\n")
-    net.close()
 
 
 if __name__ == "__main__":

@@ -639,6 +639,36 @@ def test_large_star_field_split(torch):
         assert np.all(np.abs(_np(gy[jt, it]) - oy) <= BETA_TOL * s)
 
 
+def test_star_field_of_2_28_stars_split(torch):
+    """The regime of Sec. 4 (very many stars, few rays): 2^28 stars resident
+    on the GPU (8 GiB of 32-byte records) x 256^2 rays, the star sum split
+    automatically over workgroups.  8 sampled rays match the oracle within
+    the FP64 bar, and the map equals the histogram of the per-ray bins."""
+    n = 1 << 28
+    _say("drawing 2^28 stars")
+    w = W.large_star_field(n, 256, 256)
+    rng = np.random.default_rng(28)
+    ii, jj = _sample(rng, w.rays.nx, w.rays.ny, 8)
+    with R.Context(w.lens) as ctx:
+        assert R.load().raysh_n_stars(ctx.handle) == n
+        ctx.set_star_split(0)
+        _say("gpu: split star sum")
+        gx, gy, gb = ctx.shoot(w.rays, "fp64", w.pix)
+        m = ctx.map(w.rays, w.pix, "fp64")
+        hist = torch.bincount(gb[gb >= 0].long(), minlength=w.pix.NX * w.pix.NY)
+        assert torch.equal(hist.to(torch.int32).view(w.pix.NY, w.pix.NX), m)
+        jt, it = torch.as_tensor(jj, device="cuda"), torch.as_tensor(ii, device="cuda")
+        gx, gy, gb = _np(gx[jt, it]), _np(gy[jt, it]), _np(gb[jt, it])
+    _say("oracle: 8 rays x 2^28 stars")
+    ox, oy, ob = ora.shoot_list(w.lens.as_tuple(), w.rays.as_tuple(), w.pix.as_tuple(), ii, jj)
+    tx, ty = ora.image_angles(w.rays.as_tuple())
+    s = ora.error_scale(w.lens.as_tuple(), tx[ii], ty[jj])
+    _say("max |dbeta|/S", float(np.max(np.maximum(np.abs(gx - ox), np.abs(gy - oy)) / s)))
+    assert np.all(np.abs(gx - ox) <= BETA_TOL * s)
+    assert np.all(np.abs(gy - oy) <= BETA_TOL * s)
+    _assert_bins(gb, ob, _near_edges(ox, oy, s, w.pix.as_tuple()), "2^28 stars")
+
+
 # ----------------------------------------------------------------- far-field expansion
 @pytest.mark.parametrize("block", [1, 2, 4])
 def test_expansion_matches_oracle_small(torch, small, small_oracle, block):

@@ -168,3 +168,39 @@ def test_generate_with_expansion_maps_matches_direct(torch):
     _say("expansion vs direct histograms: max L1", float(l1.max()),
          f"shooting {direct.seconds_shooting:.3f} s direct, {fast.seconds_shooting:.3f} s expansion")
     assert l1.max() < 1e-4
+
+
+# ----------------------------------------------------------------- the surrogate and its fallback
+def test_surrogate_falls_back_to_the_shooter_outside_its_domain(torch):
+    """Queries inside the training domain are answered by the network,
+    queries outside it by the plain shooter (the fallback), bit for bit what
+    shooting them gives; a query the shooter cannot answer either raises."""
+    kw = dict(rays_per_side=512, npix=128, sigmas_per_map=2, n_lo=200, n_hi=3000)
+    train = S.generate(48, seed=21, **kw)
+    net, std, _ = S.train(train, steps=200, batch=64, lr=2e-3)
+    cfg = S.ShooterConfig(rays_per_side=512, npix=128, precision="fp64")
+    sur = S.Surrogate(net, std, train, cfg, seed=77)
+    inside = train.features[:5].astype(np.float64)            # training examples: in the domain
+    outside = np.array([[0.9, 0.05, 0.5, -1.0],                # kappa above the training box
+                        [0.5, 0.3, 0.6, 0.05]])                # sigma above it
+    h, src = sur.query(np.concatenate([inside, outside]))
+    assert src.tolist() == ["network"] * 5 + ["shooter"] * 2
+    np.testing.assert_array_equal(h[:5], S.predict(net, std, inside))
+    want = S.shoot_histograms(outside, cfg, seed=77)
+    np.testing.assert_array_equal(h[5:], want)
+    assert np.allclose(h.sum(axis=1), 1.0, atol=1e-5)
+    # the fallback's histogram is the plain shooter's: the same map shot by hand
+    rng = np.random.Generator(np.random.PCG64(77))
+    lens, hx, hy = S.lens_for(0.9, 0.05, 0.5, cfg.window, rng)
+    grid = W.centred_rays(hx, hy, cfg.rays_per_side, cfg.rays_per_side)
+    pix = W.centred_window(cfg.window, cfg.npix)
+    with R.Context(lens) as ctx:
+        counts = ctx.map(grid, pix, "fp64")
+    _, h0 = S.Histogrammer(cfg.npix, cfg.npix)(counts, (grid.dx * grid.dy) / (pix.Px * pix.Py), 0.1, pix.Px,
+                                                pix.Py, W.mean_magnification(0.9, 0.05, 0.0))
+    np.testing.assert_array_equal(h[5], h0.cpu().numpy())
+    with pytest.raises(ValueError):
+        sur.query([[1.2, 0.2, 0.5, -1.0]])                     # outside the domain and critical: det A = 0
+    with pytest.raises(ValueError):
+        sur.query([[0.5, 0.3, 0.6, 0.6]])                      # a source too wide for the window
+    net.close()
