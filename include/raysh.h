@@ -227,7 +227,10 @@ int raysh_get_tile(const raysh_ctx *ctx, int precision, int *cx, int *cy, int *s
  * the block made of whole tiles, in whole rounds of the workgroups the
  * device holds at once (until about 1e11 ray-star interactions or the
  * block's own rounds); its time per round, times the rounds the whole block
- * takes, is the prediction.  cache_path (when NULL, the environment variable
+ * takes, is the prediction.  When the best prediction is at most 500 ms, the
+ * shapes predicted within 6 % of it (at most three) are then timed on the
+ * whole block (the faster of two launches each), and the fastest is kept.
+ * cache_path (when NULL, the environment variable
  * RAYSH_AUTOTUNE_CACHE; no cache if both are unset) names a text file of
  * earlier choices keyed by GPU architecture, CU count, HIP runtime version,
  * precision and log2(n_stars): a hit skips the timing, a miss appends a

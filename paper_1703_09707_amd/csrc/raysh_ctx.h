@@ -14,7 +14,7 @@ struct raysh_ctx {
     unsigned long long *d_counter = nullptr;
     unsigned long long *h_counter = nullptr;   // pinned
     // default launch shapes: the fastest on MI355X for the 16384-star workload
-    raysh::TileShape shape[2] = {{8, 4, 8, 1}, {4, 4, 0, 128}};
+    raysh::TileShape shape[2] = {{8, 4, 16, 1}, {4, 4, 0, 128}};
     int star_parts = 1;                    // FP64 split of each ray's star sum (0 = automatic)
     double theta_open = 0.25;              // far-star criterion of RAYSH_FP64_EXPANSION
     int expansion_block = 0;               // tiles per side of its workgroups (0 = automatic)

@@ -94,17 +94,23 @@ int shape_list(int precision, TileShape (&shapes)[32]) {
     return std::min(n, 32);
 }
 
+struct Timed {
+    TileShape shape;
+    double cost;
+};
+
 // Time `run` for every compiled shape: one warm-up, then the median of three
 // launches timed by HIP events on `stream`; `cost` turns a shape and its
-// median time into the figure to minimise.  Returns a RAYSH_* code.
+// median time into the figure to minimise.  Every shape's figure goes to
+// `out`, the best first.  Returns a RAYSH_* code.
 template <class Run, class Cost>
-int time_shapes(int precision, hipStream_t stream, Run run, Cost cost, TileShape &best, double &best_ms) {
+int time_shapes(int precision, hipStream_t stream, Run run, Cost cost, std::vector<Timed> &out) {
     TileShape shapes[32];
     const int n_shapes = shape_list(precision, shapes);
     hipEvent_t ev[4];
     for (auto &x : ev) (void)hipEventCreate(&x);
     int code = RAYSH_OK;
-    best_ms = -1;
+    out.clear();
     for (int i = 0; i < n_shapes && code == RAYSH_OK; ++i) {
         const TileShape &t = shapes[i];
         hipError_t e = run(t);   // warm-up
@@ -121,13 +127,11 @@ int time_shapes(int precision, hipStream_t stream, Run run, Cost cost, TileShape
             break;
         }
         std::sort(ms, ms + 3);
-        const double c = cost(t, ms[1]);
-        if (best_ms < 0 || c < best_ms) {
-            best_ms = c;
-            best = t;
-        }
+        out.push_back(Timed{t, cost(t, ms[1])});
     }
     for (auto &x : ev) (void)hipEventDestroy(x);
+    std::stable_sort(out.begin(), out.end(), [](const Timed &a, const Timed &b) { return a.cost < b.cost; });
+    if (code == RAYSH_OK && out.empty()) code = set_error(RAYSH_EINVAL, "raysh_autotune: no compiled shape");
     return code;
 }
 
@@ -141,6 +145,13 @@ void report(const TileShape &best, int *cx, int *cy, int *share, int *star_tile)
 // Interactions per timed sample: long enough (about 20 ms at the FP64 rate)
 // that the launch and the queue ramp are a small part of it.
 constexpr double kSampleWork = 1e11;
+
+// Shapes whose predicted time is within kFinalSpread of the best (at most
+// kFinalists of them) are timed on the whole block when the best prediction
+// is at most kFinalMaxMs.
+constexpr int kFinalists = 3;
+constexpr double kFinalSpread = 0.06;
+constexpr double kFinalMaxMs = 500.0;
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -202,29 +213,68 @@ extern "C" int raysh_autotune(raysh_ctx *ctx, const raysh_rays *rays, const rays
         TileShape cur{};
         ShootParams p{};
         int64_t n_tiles = 0, rounds = 1, resident = 1;
-        auto prepare = [&](const TileShape &t) {
-            if (std::memcmp(&t, &cur, sizeof t) == 0) return;
+        auto prepare = [&](const TileShape &t, bool whole) {
             cur = t;
             const int per_cu = precision == RAYSH_FP64 ? raysh::shoot_fp64_blocks_per_cu(t)
                                                        : raysh::shoot_fp32_blocks_per_cu(t);
             resident = (int64_t)per_cu * std::max(ctx->n_cu, 1);
             const raysh_rays s = shape_sample(*rays, t, ctx->n_stars, resident, n_tiles, rounds);
             p = ShootParams{};
-            fill_shoot_params(p, ctx, &s, pix);
+            fill_shoot_params(p, ctx, whole ? rays : &s, pix);
             p.counts = scratch;
         };
-        const int code = time_shapes(
+        auto launch = [&](const TileShape &t) {
+            return precision == RAYSH_FP64 ? raysh::launch_shoot_fp64(p, t, ctx->stream)
+                                           : raysh::launch_shoot_fp32(p, t, ctx->stream);
+        };
+        std::vector<Timed> ranked;
+        int code = time_shapes(
             precision, ctx->stream,
             [&](const TileShape &t) {
-                prepare(t);
-                return precision == RAYSH_FP64 ? raysh::launch_shoot_fp64(p, t, ctx->stream)
-                                               : raysh::launch_shoot_fp32(p, t, ctx->stream);
+                if (std::memcmp(&t, &cur, sizeof t) != 0) prepare(t, false);
+                return launch(t);
             },
             [&](const TileShape &t, double ms) {
-                prepare(t);
+                prepare(t, false);
                 return ms / (double)rounds * (double)ceil_div(n_tiles, resident);
             },
-            best, best_ms);
+            ranked);
+        if (code == RAYSH_OK) {
+            best = ranked[0].shape;
+            best_ms = ranked[0].cost;
+        }
+        // The finalists (predictions within kFinalSpread of the best, at most
+        // kFinalists) are timed on the whole block when it is short enough:
+        // the per-round prediction cannot see everything a long launch does
+        // (the clock it settles at, the last round's fill).
+        if (code == RAYSH_OK && best_ms <= kFinalMaxMs) {
+            hipEvent_t a, b;
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
+            double best_whole = -1;
+            for (size_t i = 0; i < ranked.size() && (int)i < kFinalists && code == RAYSH_OK; ++i) {
+                if (ranked[i].cost > best_ms * (1.0 + kFinalSpread)) break;
+                prepare(ranked[i].shape, true);
+                float fastest = 0;
+                for (int rep = 0; rep < 2 && code == RAYSH_OK; ++rep) {
+                    float ms = 0;
+                    hipError_t e = hipEventRecord(a, ctx->stream);
+                    if (e == hipSuccess) e = launch(ranked[i].shape);
+                    if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(b);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                    if (e != hipSuccess) code = hip_error(e, "raysh_autotune");
+                    if (rep == 0 || ms < fastest) fastest = ms;
+                }
+                if (code == RAYSH_OK && (best_whole < 0 || fastest < best_whole)) {
+                    best_whole = fastest;
+                    best = ranked[i].shape;
+                }
+            }
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            if (best_whole > 0) best_ms = best_whole;
+        }
         (void)hipFree(scratch);
         if (code != RAYSH_OK) return code;
         if (cache_path) cache_store(cache_path, key, best, best_ms);
@@ -287,6 +337,7 @@ extern "C" int raysh_autotune_batch(raysh_ctx *const *sets, int n_sets, const ra
         for (int s = 0; s < n_sets; ++s) old[s] = sets[s]->shape[precision];
         if (code == RAYSH_OK) {
             int inner = RAYSH_OK;
+            std::vector<Timed> ranked;
             code = time_shapes(
                 precision, lead->stream,
                 [&](const TileShape &t) {
@@ -294,8 +345,12 @@ extern "C" int raysh_autotune_batch(raysh_ctx *const *sets, int n_sets, const ra
                     inner = raysh_map_batch(sets, n_sets, sample.data(), pix, precision, maps.data());
                     return inner == RAYSH_OK ? hipSuccess : hipErrorLaunchFailure;
                 },
-                [](const TileShape &, double ms) { return ms; }, best, best_ms);
+                [](const TileShape &, double ms) { return ms; }, ranked);
             if (inner != RAYSH_OK) code = inner;   // keep the batch's own error
+            if (code == RAYSH_OK) {
+                best = ranked[0].shape;
+                best_ms = ranked[0].cost;
+            }
         }
         (void)hipStreamSynchronize(lead->stream);   // the scratch maps are still written
         for (int32_t *m : maps)

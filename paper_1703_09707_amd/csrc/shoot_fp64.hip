@@ -70,6 +70,19 @@ __device__ __forceinline__ void reciprocals(const double *r, double *inv) {
     tree_inverse<N>(r, y, inv);
 }
 
+// m / r[i] for N values that share the numerator m: the root's inverse is
+// scaled by m inside its Newton step (t = m y, then t + t e with
+// e = 1 - p y), so the leaves receive m / r[i] for one multiply per group.
+template <int N>
+__device__ __forceinline__ void scaled_reciprocals(const double *r, double m, double *inv) {
+    static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "N is a power of two");
+    const double pr = tree_product<N>(r);
+    const double y = __builtin_amdgcn_rcp(pr);
+    const double e = __builtin_fma(-pr, y, 1.0);
+    const double t = m * y;
+    tree_inverse<N>(r, __builtin_fma(t, e, t), inv);
+}
+
 __device__ __forceinline__ double mul_rn(double a, double b) {
 #pragma clang fp contract(off)
     return a * b;
@@ -92,9 +105,13 @@ template <int CX, int CY, int NS, int GX, int GY>
 __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, const double (&tx)[CX],
                                          const double (&ty)[CY], double (&ax)[CY][CX],
                                          double (&ay)[CY][CX]) {
-    // Fold the mass into the per-column and per-row offsets when that takes
-    // fewer multiplies (CX + CY per star) than weighting every ray (CX * CY).
-    constexpr bool FOLD = CX * CY > CX + CY;
+    // Where the mass enters.  One star per group (NS = 1): the whole group
+    // shares it, so it scales the group's root inverse (one multiply per
+    // group).  Otherwise it is folded into the per-column and per-row
+    // offsets when that takes fewer multiplies (CX + CY per star) than
+    // weighting every ray (CX * CY).
+    constexpr bool ROOT = NS == 1 && GX * GY > 1;
+    constexpr bool FOLD = !ROOT && CX * CY > CX + CY;
     constexpr int G = NS * GX * GY;
     int k = k0;
     // star groups are double-buffered: the next group's scalar loads are in
@@ -150,7 +167,8 @@ __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, co
                         for (int s = 0; s < NS; ++s)
                             r2[(gy * GX + gx) * NS + s] =
                                 __builtin_fma(ex[s][a0 + gx], ex[s][a0 + gx], ey2[s][b0 + gy]);
-                reciprocals<G>(r2, inv);
+                if constexpr (ROOT) scaled_reciprocals<G>(r2, sm[0], inv);
+                else reciprocals<G>(r2, inv);
 #pragma unroll
                 for (int gy = 0; gy < GY; ++gy) {
 #pragma unroll
@@ -159,7 +177,7 @@ __device__ __forceinline__ void star_sum(const ConstStar *st, int k0, int k1, co
                         for (int s = 0; s < NS; ++s) {
                             const int a = a0 + gx, b = b0 + gy;
                             const double inv1 = inv[(gy * GX + gx) * NS + s];
-                            const double w = FOLD ? inv1 : sm[s] * inv1;
+                            const double w = (FOLD || ROOT) ? inv1 : sm[s] * inv1;
                             ax[b][a] = __builtin_fma(w, mex[s][a], ax[b][a]);
                             ay[b][a] = __builtin_fma(w, mey[s][b], ay[b][a]);
                         }
@@ -486,7 +504,9 @@ hipError_t launch_split(const ShootParams &p, int parts, double2 *partial, hipSt
     X(4, 4, 16, 1)           \
     X(8, 2, 8, 1)            \
     X(8, 4, 8, 1)            \
-    X(4, 8, 8, 1)
+    X(4, 8, 8, 1)            \
+    X(8, 4, 16, 1)           \
+    X(8, 5, 8, 1)
 
 int fp64_shape_list(TileShape *out, int cap) {
     int n = 0;
