@@ -224,3 +224,36 @@ def test_track_order_entries_outside_are_skipped(torch, small_map):
             assert torch.equal(out[t], full[t])
         for t in (1, 3, 4):
             assert bool((out[t] == 1234.5).all())
+
+
+@pytest.mark.parametrize("nx,ny", [(256, 256), (300, 3), (3, 300), (7, 5), (1024, 40)])
+def test_light_curves_all_directions_and_steps(torch, nx, ny):
+    """Tracks in 16 directions with steps from a tenth of a pixel to nearly a
+    pixel, crossing the map's edges and corners, on square, thin and tiny
+    maps, in chunks that end inside a wave: bit-identical to the oracle's."""
+    rng = np.random.default_rng(nx * 1000 + ny)
+    mu_h = rng.uniform(0.1, 10.0, (ny, nx))
+    mu = torch.from_numpy(mu_h).cuda()
+    px, py = 0.013, 0.017
+    grid = (-0.4, 0.25, px, py, nx, ny)
+    xs, ys, xe, ye = [], [], [], []
+    for n in (64, 256, 257, 1000):
+        for d in range(16):
+            phi = 2 * np.pi * d / 16 + 0.01
+            for step in (0.1, 0.45, 0.499, 0.5, 0.501, 0.9):
+                length = step * (n - 1)   # in pixels along the major axis
+                c, s = np.cos(phi), np.sin(phi)
+                scale = length / max(abs(c), abs(s))
+                x0 = grid[0] + rng.uniform(-0.2, 1.2) * nx * px
+                y0 = grid[1] + rng.uniform(-0.2, 1.2) * ny * py
+                xs.append(x0)
+                ys.append(y0)
+                xe.append(x0 + scale * c * px)
+                ye.append(y0 + scale * s * py)
+        xa, ya, xb, yb = (np.array(v, np.float64) for v in (xs, ys, xe, ye))
+        dev = [torch.from_numpy(a).cuda() for a in (xa, ya, xb, yb)]
+        got = R.light_curves(mu, grid, *dev, n).cpu().numpy()
+        want = OL.light_curves(mu_h, grid, xa, ya, xb, yb, n)
+        np.testing.assert_array_equal(np.isnan(got), np.isnan(want))
+        np.testing.assert_array_equal(got, want)
+        xs, ys, xe, ye = [], [], [], []
