@@ -114,8 +114,9 @@ hipError_t build_star_cells(const Star *d_stars, int64_t n_stars, hipStream_t s,
 void free_star_cells(StarCellStore &cells);
 
 // FP64 with the far field as local expansions (shoot_expansion.hip); tiles
-// of 64 x 64 rays, one workgroup per block of `block` x `block` tiles
-// (1, 2 or 4).  expansion_block picks the block for a lattice block.  With
+// of 64 x 64 rays in blocks of `block` x `block` tiles (1, 2 or 4): one
+// workgroup per block for the pass over the stars, one per row of a block's
+// tiles for the tiles.  expansion_block picks the block for a lattice block.  With
 // cells (cells.ncx > 0) the block pass takes distant cells through their
 // multipole expansions.
 hipError_t launch_shoot_expansion(const ShootParams &p, const StarCells &cells, double theta_open, int block,

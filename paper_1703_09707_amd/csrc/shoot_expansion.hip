@@ -447,20 +447,25 @@ __global__ __launch_bounds__(kThreads, 2) void expansion_block_kernel(ShootParam
     }
 }
 
-// The tiles of a block of L x L tiles, after its block pass.  WPS waves per
-// SIMD (workgroups per compute unit).
-template <int L, int WPS>
+// The tiles of a block of L x L tiles, after its block pass: workgroup g
+// takes tiles [TPW s, TPW (s + 1)) of block g / (L^2 / TPW), s = g mod
+// (L^2 / TPW).  WPS waves per SIMD (workgroups per compute unit).
+template <int L, int TPW, int WPS>
 __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootParams p, double theta_open,
                                                                        int blocks_x,
                                                                        const BlockFar *__restrict__ far) {
+    static_assert(TPW >= 1 && (L * L) % TPW == 0, "whole groups of a block's tiles");
+    constexpr int kSubs = L * L / TPW;
     __shared__ BinShared sh;
     __shared__ ExpShared ex;
     bin_shared_init(sh);
 
     const int lx = threadIdx.x % kLanesX;
     const int ly = threadIdx.x / kLanesX;
-    const int64_t b_i = (int64_t)(blockIdx.x % blocks_x) * (kTile * L);
-    const int64_t b_j = (int64_t)(blockIdx.x / blocks_x) * (kTile * L);
+    const int blk = (int)(blockIdx.x / kSubs);
+    const int t_begin = (int)(blockIdx.x % kSubs) * TPW, t_end = t_begin + TPW;
+    const int64_t b_i = (int64_t)(blk % blocks_x) * (kTile * L);
+    const int64_t b_j = (int64_t)(blk / blocks_x) * (kTile * L);
     const ConstStar *st = const_stars(uniform_ptr(p.stars));
     const int n = uniform(p.n_stars);
     const double inv_theta = uniform_f64(1.0 / theta_open);
@@ -469,7 +474,7 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
     double bcx, bcy, brho;
     region_uniform(p, b_i, b_j, kTile * L, bcx, bcy, brho);
     {
-        const BlockFar *f = far + blockIdx.x;
+        const BlockFar *f = far + blk;
         if (threadIdx.x <= kOrder) ex.A[threadIdx.x] = f->A[threadIdx.x];
         if (threadIdx.x < kWaves) ex.outer_n[threadIdx.x] = f->outer_n[threadIdx.x];
         for (int w = 0; w < kWaves; ++w) {
@@ -485,10 +490,10 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
         n_outer += ex.outer_n[w];
     }
     if (L > 1 && !overflow) {   // uniform
-        // the block's polynomial re-centred on every tile at once
+        // the block's polynomial re-centred on every tile of the workgroup at once
         const double inv_brho = 1.0 / brho;
-        for (int idx = threadIdx.x; idx < L * L * (kOrder + 1); idx += kThreads) {
-            const int t = idx / (kOrder + 1), r = idx % (kOrder + 1);
+        for (int idx = threadIdx.x; idx < TPW * (kOrder + 1); idx += kThreads) {
+            const int t = t_begin + idx / (kOrder + 1), r = idx % (kOrder + 1);
             double cx, cy, rho;
             region(p, b_i + (int64_t)(t % L) * kTile, b_j + (int64_t)(t / L) * kTile, kTile, cx, cy, rho);
             ex.B[t][r] = shift_coeff(ex.A, r, make_double2((cx - bcx) * inv_brho, (cy - bcy) * inv_brho),
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
         __syncthreads();
     }
 
-    for (int t = 0; t < L * L; ++t) {   // uniform trip count
+    for (int t = t_begin; t < t_end; ++t) {   // uniform trip count
         const int64_t tile_i = b_i + (int64_t)(t % L) * kTile;
         const int64_t tile_j = b_j + (int64_t)(t / L) * kTile;
         if (tile_i >= p.nx || tile_j >= p.ny) continue;   // uniform: no ray of this tile is in the lattice block
@@ -601,7 +606,11 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
 
 // The block pass (with or without cells), then the tiles at three
 // workgroups per compute unit (measured faster than two at every star count
-// once the block pass is a kernel of its own).
+// once the block pass is a kernel of its own), one row of a block's tiles
+// per workgroup: L times as many workgroups as blocks, so that the last
+// round of a launch is a small part of it (on the 8192^2 lattice of 16384
+// stars, 1024 workgroups of 16 tiles filled 1.33 rounds of 768; 4096 of 4
+// tiles run 11 % faster, and rows beat 2, 8 or 16 tiles per workgroup).
 template <int L>
 hipError_t launch_level(const ShootParams &p, const StarCells &cells, double theta_open, int64_t tiles_x,
                         int64_t tiles_y, BlockFar *far, hipStream_t s) {
@@ -613,7 +622,8 @@ hipError_t launch_level(const ShootParams &p, const StarCells &cells, double the
     else
         hipLaunchKernelGGL(expansion_block_kernel<false>, grid, dim3(kThreads), 0, s, p, cells, theta_open, (int)bx,
                            kTile * L, far);
-    hipLaunchKernelGGL((expansion_fp64_kernel<L, 3>), grid, dim3(kThreads), 0, s, p, theta_open, (int)bx, far);
+    hipLaunchKernelGGL((expansion_fp64_kernel<L, L, 3>), dim3((unsigned)(bx * by * L)), dim3(kThreads), 0, s, p,
+                       theta_open, (int)bx, far);
     return hipGetLastError();
 }
 
@@ -650,20 +660,23 @@ __global__ __launch_bounds__(kThreads) void star_cell_multipole_kernel(const Sta
 
 int expansion_order() { return kOrder; }
 
-// The block that minimises a simple cost model: a workgroup costs about
-// N* + 16384 L^2 star-equivalents (its pass over all stars, then L^2 tiles
-// of Horner steps, near stars and binning, measured on MI355X), and the
-// workgroups run in rounds of three per compute unit, a part-filled round
-// counted in proportion.
+// The block that minimises a simple cost model of the two kernels, in
+// star-equivalents: the block pass runs one workgroup per block, two per
+// compute unit, each visiting all N* stars; the tile kernel runs L
+// workgroups per block, three per compute unit, each evaluating L tiles at
+// about 16384 per tile (Horner steps, near stars and binning, measured on
+// MI355X).  Rounds of resident workgroups are counted in proportion, at
+// least one (a part-filled round runs faster).
 int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu) {
     const int64_t tx = (nx + kTile - 1) / kTile, ty = (ny + kTile - 1) / kTile;
-    const int64_t slots = 3 * (int64_t)(n_cu > 0 ? n_cu : 256);
+    const double cus = (double)(n_cu > 0 ? n_cu : 256);
     int best = 1;
     double best_cost = 0.0;
     for (int L : {1, 2, 4}) {
-        const int64_t blocks = ((tx + L - 1) / L) * ((ty + L - 1) / L);
-        const double rounds = std::max(1.0, (double)blocks / (double)slots);   // a part-filled round runs faster
-        const double cost = rounds * ((double)n_stars + 16384.0 * L * L);
+        const double blocks = (double)(((tx + L - 1) / L) * ((ty + L - 1) / L));
+        const double pass = std::max(1.0, blocks / (2.0 * cus)) * (double)n_stars;
+        const double tiles = std::max(1.0, blocks * L / (3.0 * cus)) * 16384.0 * L;
+        const double cost = pass + tiles;
         if (L == 1 || cost < best_cost) {
             best = L;
             best_cost = cost;
