@@ -69,16 +69,19 @@ __device__ __forceinline__ void bin_shared_init(BinShared &sh) {
 
 // Epilogue of a ray tile: per-ray outputs, then the counts.  Each lane holds
 // CX x CY rays: column a at block index i = tile_i + lx + 16 a, row b at
-// j = tile_j + ly + 16 b.  Counts go first into an LDS window of
-// kWinX x kWinY pixels placed around the tile's mean pixel, with a global
-// atomic for rays outside it; the window is then merged into the map with
-// one global atomic per non-empty pixel.  Must be reached by every thread
-// of the workgroup (it contains barriers).
-template <int CX, int CY>
+// j = tile_j + ly + 16 b.  Counts go first into an LDS window of WX x WY
+// pixels (at most kWinX x kWinY) placed around the tile's mean pixel, with a
+// global atomic for rays outside it; the window is then merged into the map
+// with one global atomic per non-empty pixel.  With KEEP_CLEAR the window
+// must be zero on entry and is left zero (the merge clears what it reads),
+// which saves a pass over it for a caller that bins many tiles.  Must be
+// reached by every thread of the workgroup (it contains barriers).
+template <int CX, int CY, int WX = kWinX, int WY = kWinY, bool KEEP_CLEAR = false>
 __device__ __forceinline__ void finish_tile(const ShootParams &p, BinShared &sh,
                                             const double (&tx)[CX], const double (&ty)[CY],
                                             const double (&ax)[CY][CX], const double (&ay)[CY][CX],
                                             int64_t tile_i, int64_t tile_j, int lx, int ly) {
+    static_assert(WX > 0 && WY > 0 && WX * WY <= kWinX * kWinY, "the window fits BinShared");
     int32_t pis[CY][CX], pjs[CY][CX], pidx[CY][CX];
     long long s_is = 0, s_js = 0, n_in = 0;
 #pragma unroll
@@ -114,7 +117,8 @@ __device__ __forceinline__ void finish_tile(const ShootParams &p, BinShared &sh,
     s_is = wave_sum(s_is);
     s_js = wave_sum(s_js);
     n_in = wave_sum(n_in);
-    for (int t = threadIdx.x; t < kWinX * kWinY; t += kThreads) sh.win[t] = 0;
+    if (!KEEP_CLEAR)
+        for (int t = threadIdx.x; t < WX * WY; t += kThreads) sh.win[t] = 0;
     __syncthreads();   // red[] initialised at kernel start; win[] cleared
     if ((threadIdx.x & 63) == 0 && n_in > 0) {
         atomicAdd(&sh.red[0], (unsigned long long)s_is);
@@ -124,8 +128,8 @@ __device__ __forceinline__ void finish_tile(const ShootParams &p, BinShared &sh,
     __syncthreads();
     const long long total = (long long)sh.red[2];
     if (total == 0) return;   // uniform
-    const int ox = (int)((long long)sh.red[0] / total) - kWinX / 2;
-    const int oy = (int)((long long)sh.red[1] / total) - kWinY / 2;
+    const int ox = (int)((long long)sh.red[0] / total) - WX / 2;
+    const int oy = (int)((long long)sh.red[1] / total) - WY / 2;
 #pragma unroll
     for (int b = 0; b < CY; ++b) {
 #pragma unroll
@@ -133,18 +137,19 @@ __device__ __forceinline__ void finish_tile(const ShootParams &p, BinShared &sh,
             if (pidx[b][a] < 0) continue;
             const unsigned wx = (unsigned)(pis[b][a] - ox);
             const unsigned wy = (unsigned)(pjs[b][a] - oy);
-            if (wx < (unsigned)kWinX && wy < (unsigned)kWinY)
-                atomicAdd(&sh.win[wy * kWinX + wx], 1);
+            if (wx < (unsigned)WX && wy < (unsigned)WY)
+                atomicAdd(&sh.win[wy * WX + wx], 1);
             else
                 atomicAdd(&p.counts[pidx[b][a]], 1);
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < kWinX * kWinY; t += kThreads) {
+    for (int t = threadIdx.x; t < WX * WY; t += kThreads) {
         const int v = sh.win[t];
+        if (KEEP_CLEAR && v) sh.win[t] = 0;
         if (v) {
-            const int gx = ox + (t % kWinX);
-            const int gy = oy + (t / kWinX);
+            const int gx = ox + (t % WX);
+            const int gy = oy + (t / WX);
             if (gx >= 0 && gx < p.NX && gy >= 0 && gy < p.NY)
                 atomicAdd(&p.counts[gy * p.NX + gx], v);
         }

@@ -459,6 +459,7 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
     __shared__ BinShared sh;
     __shared__ ExpShared ex;
     bin_shared_init(sh);
+    for (int t = threadIdx.x; t < kWinX * kWinY; t += kThreads) sh.win[t] = 0;   // kept clear by finish_tile
 
     const int lx = threadIdx.x % kLanesX;
     const int ly = threadIdx.x / kLanesX;
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(kThreads, WPS) void expansion_fp64_kernel(ShootPara
                 for (int a = 0; a < kCX; ++a) macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
             for (int k = 0; k < n; ++k) direct_star(st, k, tx, ty, ax, ay);
         }
-        finish_tile<kCX, kCY>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
+        finish_tile<kCX, kCY, kWinX, kWinY, true>(p, sh, tx, ty, ax, ay, tile_i, tile_j, lx, ly);
         __syncthreads();   // the bin window, red[], B and the inner lists are reused by the next tile
         bin_shared_init(sh);
     }
