@@ -43,7 +43,7 @@ FLOP_PER_INTERACTION = 10
 PROFILE = os.path.join(ROOT, "profiles", "shoot_fp64_kernel_plain-fp64-large.txt")
 PROFILE_LC = os.path.join(ROOT, "profiles", "light_curve_track_kernel_light-curves-large.txt")
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
-# FP32 without packed instructions (not used by this build) issues at the FP64 rate
+# FP32 without packed instructions (the library is compiled without them) issues at the FP64 rate
 FP32_VECTOR_PEAK_TFLOPS = 78.6
 PROFILE_FP32 = os.path.join(ROOT, "profiles", "shoot_fp32_kernel_plain-fp64-large.txt")
 METRIC = "Gray-star interactions/s and rays/s at 1 GPU (FP64 vs FP32-bulk), % vector peak"
@@ -501,8 +501,8 @@ def main():
             "tile": list(tile32),
             "roofline": {"bound": "alu", "achieved": ach32, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": ach32 / FP32_VECTOR_PEAK_TFLOPS, "kernel": "shoot_fp32_kernel",
-                         "peak_note": "FP32 vector peak without packed instructions (packed FP32 is off in "
-                                      "this build); 157.3 TFLOP/s with them",
+                         "peak_note": "FP32 vector peak without packed instructions (the library is compiled "
+                                      "without them); 157.3 TFLOP/s with them",
                          "traffic": measured_traffic("plain-fp64-large tile32 %d,%d,%d,%d" % tile32,
                                                      PROFILE_FP32, "shoot_fp32_kernel"),
                          "kernel_ms": k32, "flop_per_launch": FLOP_PER_INTERACTION * inter}}

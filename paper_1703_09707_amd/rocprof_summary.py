@@ -1,10 +1,10 @@
 """Short text summaries of rocprofv3 runs (rocpd SQLite databases).
 
     python -m paper_1703_09707_amd.rocprof_summary --kernel shoot_fp64_kernel \\
-        --stats gpurun_out/prof_stats/bench_results.db \\
-        --fetch gpurun_out/prof_fetch/bench_results.db \\
-        --write gpurun_out/prof_write/bench_results.db \\
-        --valu gpurun_out/prof_valu/bench_results.db \\
+        --stats prof_stats/bench_results.db \\
+        --fetch prof_fetch/bench_results.db \\
+        --write prof_write/bench_results.db \\
+        --valu prof_valu/bench_results.db \\
         --copy-mib 1024 --command "..." --out profiles/<kernel>_<workload>.txt
 
 HBM byte counters are scaled by what the same counter reads for a plain copy
