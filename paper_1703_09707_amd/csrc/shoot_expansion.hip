@@ -661,23 +661,25 @@ __global__ __launch_bounds__(kThreads) void star_cell_multipole_kernel(const Sta
 
 int expansion_order() { return kOrder; }
 
-// The block that minimises a simple cost model of the two kernels, in
-// star-equivalents: the block pass runs one workgroup per block, two per
-// compute unit, each visiting all N* stars; the tile kernel runs L
-// workgroups per block, three per compute unit, each evaluating L tiles at
-// about 16384 per tile (Horner steps, near stars and binning, measured on
-// MI355X).  Rounds of resident workgroups are counted in proportion, at
-// least one (a part-filled round runs faster).
+// The block that minimises a simple cost model fitted on MI355X: a block
+// costs about N* + 16384 L^2 star-equivalents (its pass over all stars,
+// then L^2 tiles of Horner steps, near stars and binning), and blocks run in
+// rounds of three per compute unit, a part-filled round counted in
+// proportion.  The tiles of a block run as L workgroups, but the model
+// keeps their sum: it also keeps large blocks away from lattices of few
+// blocks, where dense star fields would overflow a large block's near-star
+// lists (then its tiles sum every star directly).  Counting the tile
+// workgroups as separate work picked 4 x 4 blocks for the 4096^2-ray maps
+// of 512 to 50 000 stars, five times slower than 2 x 2.
 int expansion_block(int64_t nx, int64_t ny, int64_t n_stars, int n_cu) {
     const int64_t tx = (nx + kTile - 1) / kTile, ty = (ny + kTile - 1) / kTile;
-    const double cus = (double)(n_cu > 0 ? n_cu : 256);
+    const int64_t slots = 3 * (int64_t)(n_cu > 0 ? n_cu : 256);
     int best = 1;
     double best_cost = 0.0;
     for (int L : {1, 2, 4}) {
-        const double blocks = (double)(((tx + L - 1) / L) * ((ty + L - 1) / L));
-        const double pass = std::max(1.0, blocks / (2.0 * cus)) * (double)n_stars;
-        const double tiles = std::max(1.0, blocks * L / (3.0 * cus)) * 16384.0 * L;
-        const double cost = pass + tiles;
+        const int64_t blocks = ((tx + L - 1) / L) * ((ty + L - 1) / L);
+        const double rounds = std::max(1.0, (double)blocks / (double)slots);   // a part-filled round runs faster
+        const double cost = rounds * ((double)n_stars + 16384.0 * L * L);
         if (L == 1 || cost < best_cost) {
             best = L;
             best_cost = cost;
