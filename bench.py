@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate section")
     ap.add_argument("--surrogate-steps", type=int, default=20000, help="training steps of the surrogate section")
     ap.add_argument("--runs", type=int, default=5, help="runs per secondary timing (median reported)")
+    ap.add_argument("--no-probe", action="store_true", help="skip the FMA-rate probe")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer 3 times (the reference kernel for "
                          "scaling HBM byte counters)")
@@ -94,6 +95,41 @@ def measured_traffic(workload_tag, profile=PROFILE, kernel="shoot_fp64_kernel"):
     if s.get("source_sha256") != RS.source_hash(kernel) or s.get("workload") != workload_tag:
         return None
     return float(s["traffic_bytes_per_launch"])
+
+
+# The FMA probe: 2048 workgroups of 256 threads, 8 chains of 16384 FMAs per
+# thread (1.07e9 wave-level FMA instructions, 1.37e11 FLOP per launch).
+PROBE_BLOCKS = 2048
+PROBE_ITERS = 16384
+
+
+def fma_probe_section(torch, raysh, runs, skip_fp32):
+    """Plain FMA rate of the box at the clock it holds right after the FP64
+    maps: the probe kernel issues nothing but independent FMAs, so its rate
+    is the most the vector ALUs sustain here, beside the datasheet peak
+    (78.6 TFLOP/s at 2.4 GHz).  Its results are exact, and are checked."""
+    out = {"workload": f"{PROBE_BLOCKS} x 256 threads x 8 chains x {PROBE_ITERS} FMA",
+           "wave_fma_instructions": PROBE_BLOCKS * 4 * 8 * PROBE_ITERS}
+    flop = 2.0 * PROBE_BLOCKS * 256 * 8 * PROBE_ITERS
+    lane = torch.arange(PROBE_BLOCKS * 256, device="cuda") % 64
+    for prec in ("fp64",) + (() if skip_fp32 else ("fp32_bulk",)):
+        buf = raysh.fma_probe(prec, PROBE_BLOCKS, PROBE_ITERS)
+        want = (8 * (lane + PROBE_ITERS) + 28).to(buf.dtype)   # sum over chains i < 8 of (lane + i + iters)
+        if not bool(torch.equal(buf, want)):
+            raise RuntimeError(f"FMA probe ({prec}) returned wrong values")
+        ms = []
+        for _ in range(max(runs, 5)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            raysh.fma_probe(prec, PROBE_BLOCKS, PROBE_ITERS, out=buf)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        t = sorted(ms)[len(ms) // 2]
+        tf = flop / (t * 1e-3) / 1e12
+        out[prec] = {"kernel_ms": t, "tflops": tf, "frac_of_peak": tf / FP64_VECTOR_PEAK_TFLOPS,
+                     "clock_ghz_if_every_cycle_issues": tf / FP64_VECTOR_PEAK_TFLOPS * 2.4}
+    return out
 
 
 def time_steps(torch, ctx, w, precision, counts, steps, warmup):
@@ -477,6 +513,9 @@ def main():
                      "kernel_ms": k_avg,
                      "flop_per_launch": FLOP_PER_INTERACTION * inter},
     }
+    if not args.no_probe:
+        print("# FMA probe", file=sys.stderr, flush=True)
+        out["fma_probe"] = fma_probe_section(torch, raysh, args.runs, args.no_fp32)
     if not args.no_fp32:
         print("# fp32_bulk", file=sys.stderr, flush=True)
         c32 = torch.zeros_like(counts)

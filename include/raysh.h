@@ -513,6 +513,21 @@ int raysh_mlp_train_step(raysh_mlp *mlp, const float *x, const float *target, in
 int raysh_mlp_sync(raysh_mlp *mlp);
 int raysh_mlp_free(raysh_mlp *mlp);
 
+/*
+ * raysh_fma_probe: a measurement aid for profilers, not part of the method.
+ * Runs n_blocks workgroups of 256 threads; each thread keeps 8 independent
+ * chains a <- fma(a, 1, 1) for n_iter steps and stores the sum of its chains
+ * in out[block * 256 + thread] (device memory: double for RAYSH_FP64, float
+ * for RAYSH_FP32_BULK).  Each wave issues exactly 8 * n_iter FMA
+ * instructions of that precision and 7 adds, so a counter of FMA
+ * instructions and the achieved FMA rate can be checked against known
+ * numbers.  Every step is exact: thread t stores
+ * sum over i < 8 of ((t mod 64) + i + n_iter).  Asynchronous on hip_stream,
+ * on out's device.  EINVAL on another precision, n_blocks outside
+ * [1, 2^31-1], n_iter < 1, or a NULL, non-device or short buffer.
+ */
+int raysh_fma_probe(int precision, int64_t n_blocks, int32_t n_iter, void *out, void *hip_stream);
+
 /* Wait for all work enqueued by the context. */
 int raysh_sync(raysh_ctx *ctx);
 

@@ -12,7 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libraysh.so")
 SOURCES = ["raysh_api.hip", "raysh_batch.hip", "raysh_tune.hip", "shoot_fp64.hip",
-           "shoot_fp32.hip", "shoot_expansion.hip", "histogram.hip", "light_curves.hip", "mlp.hip"]
+           "shoot_fp32.hip", "shoot_expansion.hip", "histogram.hip", "light_curves.hip", "mlp.hip",
+           "fma_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wall", "-Wno-unused-function",

@@ -39,7 +39,7 @@ EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", 
            "raysh_map_batch",
            "raysh_histogram_workspace", "raysh_log_mag_histogram",
            "raysh_source_map_shape", "raysh_source_map_workspace", "raysh_source_map", "raysh_light_curves",
-           "raysh_track_order_workspace", "raysh_track_order",
+           "raysh_track_order_workspace", "raysh_track_order", "raysh_fma_probe",
            "raysh_mlp_create",
            "raysh_mlp_n_params", "raysh_mlp_get_params", "raysh_mlp_forward", "raysh_mlp_gradient",
            "raysh_mlp_adam_step", "raysh_mlp_train_step", "raysh_mlp_sync", "raysh_mlp_free",
@@ -129,6 +129,8 @@ def load():
     lib.raysh_track_order.argtypes = [ctypes.POINTER(Pixels), ctypes.c_int64, P, P, P, P, P, ctypes.c_size_t, P, P,
                                       P]
     lib.raysh_track_order.restype = I
+    lib.raysh_fma_probe.argtypes = [I, ctypes.c_int64, ctypes.c_int32, P, P]
+    lib.raysh_fma_probe.restype = I
     F = ctypes.c_float
     lib.raysh_mlp_create.argtypes = [ctypes.POINTER(P), I, P, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32, P]
@@ -426,6 +428,21 @@ def track_order(grid, xa, ya, xb, yb, sorted_end_points=False, stream=None):
     check(lib.raysh_track_order(ctypes.byref(g), n, _ptr(xa), _ptr(ya), _ptr(xb), _ptr(yb), _ptr(ws), ws.numel(),
                                 _ptr(order), _ptr(srt), _stream_handle(torch, xa.device, stream)))
     return (order, srt) if sorted_end_points else order
+
+
+def fma_probe(precision, n_blocks, n_iter, out=None, stream=None):
+    """raysh_fma_probe: a kernel of exactly 8 * n_iter FMA instructions per
+    wave (a measurement aid).  Returns the device array of n_blocks * 256
+    values (FP64 for "fp64", FP32 for "fp32_bulk")."""
+    torch = _torch()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    dtype = torch.float64 if prec == FP64 else torch.float32
+    if out is None:
+        out = torch.empty(int(n_blocks) * 256, dtype=dtype, device="cuda")
+    assert out.dtype == dtype and out.is_contiguous() and out.numel() >= int(n_blocks) * 256
+    check(load().raysh_fma_probe(prec, int(n_blocks), int(n_iter), _ptr(out),
+                                 _stream_handle(torch, out.device, stream)))
+    return out
 
 
 def light_curves(mu_s, grid, xa, ya, xb, yb, n_samples, out=None, order=None, sorted=None, stream=None):

@@ -120,6 +120,29 @@ def pmc_lines(dbs, kernel, grid, n_cu):
     return out
 
 
+def probe_lines(valu_db, stats_db, precision, expected_fma):
+    """The FMA probe (raysh_fma_probe) profiled in the same run: its FMA
+    counter per dispatch against the wave-level FMA instructions it is known
+    to issue, and the FLOP rate the counters then give over its time."""
+    P = precision.upper()
+    name = "fma_probe_kernel<double>" if precision == "f64" else "fma_probe_kernel<float>"
+    vals = counter_values(valu_db, name)
+    fma = vals.get(f"SQ_INSTS_VALU_FMA_{P}")
+    out = [f"FMA probe ({name}, the counters' calibration):"]
+    if not fma:
+        return out + ["  not in this run"]
+    counted = sum(fma) / len(fma)
+    out.append(f"  SQ_INSTS_VALU_FMA_{P} per dispatch: {counted:.6e}  (known: {expected_fma:.6e} wave "
+               f"instructions; ratio {counted / expected_fma:.4f})")
+    durs = dispatch_durations_us(stats_db, name) or dispatch_durations_us(valu_db, name)
+    if durs:
+        us = sorted(durs)[len(durs) // 2]
+        tflops = 64 * 2 * counted / (us * 1e-6) / 1e12
+        out.append(f"  median duration {us:.1f} us: 64 lanes x 2 FLOP x the counter = {tflops:.2f} TFLOP/s "
+                   f"({tflops / 78.6:.3f} of 78.6)")
+    return out
+
+
 def read_summary(path):
     """key: value pairs of a summary file (None if missing)."""
     if not os.path.exists(path):
@@ -152,6 +175,9 @@ def main(argv=None):
                     help="more --pmc databases: every counter of the kernel is listed, and those counted in "
                          "cycles also as a fraction of the CUs' cycles (GRBM_GUI_ACTIVE in one of them)")
     ap.add_argument("--n-cu", type=int, default=256)
+    ap.add_argument("--probe-fma", type=float, default=None,
+                    help="wave-level FMA instructions per dispatch of the FMA probe in the --valu run: "
+                         "the summary checks the counter against it")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
@@ -229,6 +255,8 @@ def main(argv=None):
             if a.flop_per_launch:
                 lines.append(f"algorithmic_flop_per_launch: {a.flop_per_launch:.6e}")
                 lines.append(f"counter_over_algorithmic: {f64 / a.flop_per_launch:.4f}")
+    if a.valu and a.probe_fma:
+        lines += [""] + probe_lines(a.valu, a.stats, a.precision, a.probe_fma)
     if a.pmc:
         lines += [""] + pmc_lines(a.pmc, a.kernel, a.grid, a.n_cu)
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)

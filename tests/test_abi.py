@@ -261,3 +261,14 @@ def test_source_map_and_light_curve_argument_errors(lib):
     assert "workspace" in _err(lib)
     assert to(ctypes.byref(g), 4, d, None, d, d, d, 1 << 30, d, None, None) == R.EINVAL
     assert to(ctypes.byref(g), 0, None, None, None, None, None, 0, None, None, None) == R.OK
+
+
+def test_fma_probe_argument_errors(lib):
+    d = ctypes.c_void_p(1)
+    assert lib.raysh_fma_probe(R.FP64_EXPANSION, 1, 1, d, None) == R.EINVAL
+    assert "precision" in _err(lib)
+    assert lib.raysh_fma_probe(R.FP64, 0, 1, d, None) == R.EINVAL
+    assert lib.raysh_fma_probe(R.FP32_BULK, 1 << 31, 1, d, None) == R.EINVAL
+    assert lib.raysh_fma_probe(R.FP64, 1, 0, d, None) == R.EINVAL
+    assert "n_iter" in _err(lib)
+    assert lib.raysh_fma_probe(R.FP64, 1, 1, None, None) == R.EINVAL
