@@ -18,12 +18,13 @@
 // sum (Sec. 1); this is a two-level form of that idea, on the ray side,
 // whose truncation error stays at the level of FP64 rounding.
 //
-// Two levels.  A workgroup owns a block of L x L ray tiles (a tile is
-// 64 x 64 rays, 4 x 4 per lane as in the one-pass kernel).  It expands the
-// stars far from the whole block once (every star is visited once per
-// block, not once per tile), keeping the block's near stars in lists, and
-// re-centres the block's polynomial on every tile at once (the shift of a
-// polynomial is exact algebra: no new truncation).  For each tile it then
+// Two levels.  The lattice is cut into blocks of L x L ray tiles (a tile is
+// 64 x 64 rays, 4 x 4 per lane as in the one-pass kernel).  One workgroup
+// per block expands the stars far from the whole block once (every star is
+// visited once per block, not once per tile), keeping the block's near
+// stars in lists.  Then one workgroup per row of the block's tiles
+// re-centres the block's polynomial on each of its tiles (the shift of a
+// polynomial is exact algebra: no new truncation), and for each tile
 //   * re-tests only the block's near stars: those far from the tile join
 //     its polynomial, the rest are summed directly,
 //   * evaluates the polynomial for its rays (Horner), adds the near stars

@@ -26,10 +26,12 @@
 // with a non-finite sum are therefore summed again one by one with a
 // division per star, so that only a ray that sits on a star is dropped, as
 // the plain definition drops it.
-// The mass multiplies either the per-column and per-row offsets (when a lane
-// owns more rays than it has rows plus columns) or 1/r^2 of each ray; the
-// accumulation alpha += (m/r^2)(theta - theta_k) is one FMA per component,
-// stars in index order.
+// The mass enters where it costs least: for groups of one star and several
+// rays, at the root of the product tree (one multiply per group, and the
+// leaves receive m/r^2); otherwise in the per-column and per-row offsets
+// when a lane owns more rays than it has rows plus columns, else in 1/r^2
+// of each ray.  The accumulation alpha += (m/r^2)(theta - theta_k) is one
+// FMA per component, stars in index order.
 #include "ray_common.h"
 
 namespace raysh {
