@@ -203,17 +203,25 @@ def test_band_additivity(torch, small):
 
 
 def test_zero_stars_and_massless_star(torch, small):
-    """n_stars = 0 is a pure sheet; a massless star changes nothing."""
+    """n_stars = 0 is a pure sheet; a massless star changes nothing: in FP64
+    (one pass and split), FP32-bulk and the expansion mode."""
     lens0 = (small.lens.kappa_c, small.lens.gamma1, small.lens.gamma2, [], [], [])
     lens1 = (small.lens.kappa_c, small.lens.gamma1, small.lens.gamma2, [0.3], [0.7], [0.0])
     rays = small.rays.block(100, 100, 200, 150)
     ox, oy, ob = ora.shoot(lens0, rays.as_tuple(), small.pix.as_tuple())
     for lens in (lens0, lens1):
         with R.Context(lens) as ctx:
-            gx, gy, gb = ctx.shoot(rays, "fp64", small.pix)
-            np.testing.assert_array_equal(_np(gx), ox)
-            np.testing.assert_array_equal(_np(gy), oy)
-            np.testing.assert_array_equal(_np(gb), ob)
+            # every path adds an exact zero to the macro term: the same beta bit for bit
+            for prec, split in (("fp64", 1), ("fp64", 4), ("fp32_bulk", 1), ("fp64_expansion", 1)):
+                ctx.set_star_split(split)
+                gx, gy, gb = ctx.shoot(rays, prec, small.pix)
+                np.testing.assert_array_equal(_np(gx), ox, err_msg=f"{prec} split {split}")
+                np.testing.assert_array_equal(_np(gy), oy, err_msg=f"{prec} split {split}")
+                np.testing.assert_array_equal(_np(gb), ob, err_msg=f"{prec} split {split}")
+            ctx.set_star_split(1)
+            m = ctx.map(rays, small.pix, "fp64")
+            want = np.bincount(ob[ob >= 0], minlength=small.pix.NX * small.pix.NY)
+            np.testing.assert_array_equal(_np(m).ravel(), want)
 
 
 def test_fp32_bulk_small(torch, small, small_oracle):
