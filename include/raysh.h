@@ -128,6 +128,23 @@ typedef struct raysh_ctx raysh_ctx;
  */
 int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_stream);
 
+/*
+ * raysh_set_lens: give an existing context another lens (kappa_c, gamma and
+ * star field), as raysh_init would, without creating a context: for runs of
+ * many maps of different lenses (the grids of simulations of Sec. 1 and
+ * Sec. 2.2).  Waits for the work enqueued on the context's stream (it used
+ * the old stars), then copies the new stars into the context's device
+ * buffer, growing it when the field is larger (by half again at least),
+ * and returns when they are on the device; the caller may then free its
+ * arrays.  Captured batch launches that include the context and its star
+ * cells are dropped (built again when next used); launch shapes and
+ * workspaces are kept.  The context keeps the pinned staging buffers of its
+ * uploads (2 x min(N*, 2^19) records of 32 bytes) until raysh_free.
+ * Errors as raysh_init (EINVAL also for ctx == NULL); on EINVAL or ENOMEM
+ * the context keeps its old lens; after EDEVICE its lens is undefined.
+ */
+int raysh_set_lens(raysh_ctx *ctx, const raysh_lens *lens);
+
 /* Redirect the context's work to another HIP stream of the same device. */
 int raysh_set_stream(raysh_ctx *ctx, void *hip_stream);
 

@@ -139,40 +139,75 @@ int launch(raysh_ctx *c, const ShootParams &p, int precision, const char *what) 
 // Star records go to the device through two pinned staging buffers of
 // kUploadChunk records, packed on the host while the other one is copied,
 // so the host holds 2 x 16 MiB at any N* instead of a second copy of the
-// star field.  Synchronous: returns when every record is on the device.
+// star field.  The buffers stay with the context (raysh_set_lens uploads
+// through them again).  Synchronous: returns when every record is on the
+// device.
 constexpr size_t kUploadChunk = size_t(1) << 19;
 
 hipError_t upload_stars(raysh_ctx *c, const raysh_lens *lens, size_t total) {
     const size_t per = std::min(kUploadChunk, total);
     const int n_buf = total > per ? 2 : 1;
-    Star *stage[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    if (c->stage_records < per) {
+        for (int b = 0; b < 2; ++b) {
+            if (c->h_stage[b]) (void)hipHostFree(c->h_stage[b]);
+            c->h_stage[b] = nullptr;
+        }
+        c->stage_records = per;
+    }
+    for (int b = 0; b < n_buf && e == hipSuccess; ++b)
+        if (!c->h_stage[b]) e = hipHostMalloc((void **)&c->h_stage[b], c->stage_records * sizeof(Star),
+                                              hipHostMallocDefault);
     hipEvent_t done[2] = {nullptr, nullptr};
     bool pending[2] = {false, false};
-    hipError_t e = hipSuccess;
-    for (int b = 0; b < n_buf && e == hipSuccess; ++b) {
-        e = hipHostMalloc((void **)&stage[b], per * sizeof(Star), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&done[b], hipEventDisableTiming);
-    }
+    for (int b = 0; b < n_buf && e == hipSuccess; ++b) e = hipEventCreateWithFlags(&done[b], hipEventDisableTiming);
     for (size_t off = 0, b = 0; off < total && e == hipSuccess; off += per, b = (b + 1) % n_buf) {
         const size_t cnt = std::min(per, total - off);
         if (pending[b]) e = hipEventSynchronize(done[b]);   // the buffer's last copy has finished
         if (e != hipSuccess) break;
+        Star *stage = c->h_stage[b];
         for (size_t k = 0; k < cnt; ++k) {
             const size_t i = off + k;
-            stage[b][k] = (int64_t)i < lens->n_stars ? Star{lens->x[i], lens->y[i], lens->m[i], 0.0}
-                                                      : Star{0.0, 0.0, 0.0, 0.0};
+            stage[k] = (int64_t)i < lens->n_stars ? Star{lens->x[i], lens->y[i], lens->m[i], 0.0}
+                                                   : Star{0.0, 0.0, 0.0, 0.0};
         }
-        e = hipMemcpyAsync(c->d_stars + off, stage[b], cnt * sizeof(Star), hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(c->d_stars + off, stage, cnt * sizeof(Star), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipEventRecord(done[b], c->stream);
         pending[b] = e == hipSuccess;
     }
-    const hipError_t s = hipStreamSynchronize(c->stream);   // also before the buffers are freed
+    const hipError_t s = hipStreamSynchronize(c->stream);   // the staging buffers are free again
     if (e == hipSuccess) e = s;
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < 2; ++b)
         if (done[b]) (void)hipEventDestroy(done[b]);
-        if (stage[b]) (void)hipHostFree(stage[b]);
-    }
     return e;
+}
+
+// The checks raysh_init and raysh_set_lens make on a lens.
+int validate_lens(const raysh_lens *lens) {
+    if (!lens) return set_error(RAYSH_EINVAL, "lens is NULL");
+    if (!std::isfinite(lens->kappa_c) || !std::isfinite(lens->gamma1) || !std::isfinite(lens->gamma2))
+        return set_error(RAYSH_EINVAL, "kappa_c and gamma must be finite");
+    if (lens->n_stars < 0) return set_error(RAYSH_EINVAL, "n_stars < 0");
+    if (lens->n_stars > std::numeric_limits<int32_t>::max())
+        return set_error(RAYSH_EOVERFLOW, "n_stars > 2^31-1");
+    const int64_t n = lens->n_stars;
+    if (n > 0 && (!lens->x || !lens->y || !lens->m)) return set_error(RAYSH_EINVAL, "star array is NULL");
+    for (int64_t k = 0; k < n; ++k) {
+        if (!std::isfinite(lens->x[k]) || !std::isfinite(lens->y[k]))
+            return set_error(RAYSH_EINVAL, "star %lld position is not finite", (long long)k);
+        if (!std::isfinite(lens->m[k]) || lens->m[k] < 0)
+            return set_error(RAYSH_EINVAL, "star %lld mass is negative or not finite", (long long)k);
+    }
+    return RAYSH_OK;
+}
+
+void set_macro(raysh_ctx *c, const raysh_lens *lens) {
+    c->kappa_c = lens->kappa_c;
+    c->gamma1 = lens->gamma1;
+    c->gamma2 = lens->gamma2;
+    c->k11 = lens->kappa_c + lens->gamma1;
+    c->k12 = lens->gamma2;
+    c->k22 = lens->kappa_c - lens->gamma1;
 }
 
 }  // namespace
@@ -296,20 +331,8 @@ const char *raysh_last_error(void) { return g_err; }
 
 int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_stream) {
     if (!out) return set_error(RAYSH_EINVAL, "out is NULL");
-    if (!lens) return set_error(RAYSH_EINVAL, "lens is NULL");
-    if (!std::isfinite(lens->kappa_c) || !std::isfinite(lens->gamma1) || !std::isfinite(lens->gamma2))
-        return set_error(RAYSH_EINVAL, "kappa_c and gamma must be finite");
-    if (lens->n_stars < 0) return set_error(RAYSH_EINVAL, "n_stars < 0");
-    if (lens->n_stars > std::numeric_limits<int32_t>::max())
-        return set_error(RAYSH_EOVERFLOW, "n_stars > 2^31-1");
+    if (int r = validate_lens(lens)) return r;
     const int64_t n = lens->n_stars;
-    if (n > 0 && (!lens->x || !lens->y || !lens->m)) return set_error(RAYSH_EINVAL, "star array is NULL");
-    for (int64_t k = 0; k < n; ++k) {
-        if (!std::isfinite(lens->x[k]) || !std::isfinite(lens->y[k]))
-            return set_error(RAYSH_EINVAL, "star %lld position is not finite", (long long)k);
-        if (!std::isfinite(lens->m[k]) || lens->m[k] < 0)
-            return set_error(RAYSH_EINVAL, "star %lld mass is negative or not finite", (long long)k);
-    }
     if (device < 0) return set_error(RAYSH_EINVAL, "device < 0");
     int n_dev = 0;
     hipError_t e = hipGetDeviceCount(&n_dev);
@@ -325,12 +348,7 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->n_stars = n;
-    c->kappa_c = lens->kappa_c;
-    c->gamma1 = lens->gamma1;
-    c->gamma2 = lens->gamma2;
-    c->k11 = lens->kappa_c + lens->gamma1;
-    c->k12 = lens->gamma2;
-    c->k22 = lens->kappa_c - lens->gamma1;
+    set_macro(c, lens);
     if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
         (void)hipGetLastError();
         c->n_cu = 1;
@@ -343,6 +361,7 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
         delete c;
         return set_error(RAYSH_ENOMEM, "device allocation of %zu stars failed", total);
     }
+    c->star_capacity = (int64_t)total;
     e = hipMalloc(&c->d_counter, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipHostMalloc(&c->h_counter, sizeof(unsigned long long), hipHostMallocDefault);
     if (e == hipSuccess) e = upload_stars(c, lens, total);
@@ -352,6 +371,39 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
         return code;
     }
     *out = c;
+    return set_ok();
+}
+
+int raysh_set_lens(raysh_ctx *ctx, const raysh_lens *lens) {
+    if (!ctx) return set_error(RAYSH_EINVAL, "ctx is NULL");
+    if (int r = validate_lens(lens)) return r;
+    const int64_t n = lens->n_stars;
+    const size_t total = (size_t)(n > 0 ? n : 1);   // one zero record when there are no stars
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    // work enqueued before this call reads the old stars
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_error(e, "raysh_set_lens");
+    if ((int64_t)total > ctx->star_capacity) {
+        // grow by half again at least, so that a run of growing fields reallocates rarely
+        const size_t cap = std::max(total, (size_t)ctx->star_capacity + (size_t)ctx->star_capacity / 2);
+        Star *grown = nullptr;
+        e = hipMalloc(&grown, cap * sizeof(Star));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(RAYSH_ENOMEM, "raysh_set_lens: device allocation of %zu stars failed", cap);
+        }
+        (void)hipFree(ctx->d_stars);
+        ctx->d_stars = grown;
+        ctx->star_capacity = (int64_t)cap;
+    }
+    raysh_forget_batches(ctx);             // captured batches hold the old star count
+    raysh::free_star_cells(ctx->cells);    // built again, from the new stars, when used
+    ctx->cells_built = false;
+    ctx->n_stars = n;
+    set_macro(ctx, lens);
+    e = upload_stars(ctx, lens, total);
+    if (e != hipSuccess) return hip_error(e, "raysh_set_lens");
     return set_ok();
 }
 
@@ -558,6 +610,8 @@ int raysh_free(raysh_ctx *ctx) {
         if (ctx->d_partial) (void)hipFree(ctx->d_partial);
         if (ctx->d_far) (void)hipFree(ctx->d_far);
         if (ctx->h_counter) (void)hipHostFree(ctx->h_counter);
+        for (int b = 0; b < 2; ++b)
+            if (ctx->h_stage[b]) (void)hipHostFree(ctx->h_stage[b]);
         raysh::free_star_cells(ctx->cells);
     }
     delete ctx;

@@ -9,6 +9,9 @@ struct raysh_ctx {
     hipStream_t stream = nullptr;
     int64_t n_stars = 0;
     raysh::Star *d_stars = nullptr;        // n_stars records (at least one allocated)
+    int64_t star_capacity = 0;             // records d_stars holds
+    raysh::Star *h_stage[2] = {nullptr, nullptr};   // pinned staging of star uploads, kept for raysh_set_lens
+    size_t stage_records = 0;              // records each staging buffer holds
     double kappa_c = 0, gamma1 = 0, gamma2 = 0;
     double k11 = 0, k12 = 0, k22 = 0;      // K of Eq. (3)
     unsigned long long *d_counter = nullptr;

@@ -39,7 +39,7 @@ EXPORTS = ("raysh_init", "raysh_set_stream", "raysh_n_stars", "raysh_set_tile", 
            "raysh_map_batch",
            "raysh_histogram_workspace", "raysh_log_mag_histogram",
            "raysh_source_map_shape", "raysh_source_map_workspace", "raysh_source_map", "raysh_light_curves",
-           "raysh_track_order_workspace", "raysh_track_order", "raysh_fma_probe",
+           "raysh_track_order_workspace", "raysh_track_order", "raysh_fma_probe", "raysh_set_lens",
            "raysh_mlp_create",
            "raysh_mlp_n_params", "raysh_mlp_get_params", "raysh_mlp_forward", "raysh_mlp_gradient",
            "raysh_mlp_adam_step", "raysh_mlp_train_step", "raysh_mlp_sync", "raysh_mlp_free",
@@ -129,6 +129,8 @@ def load():
     lib.raysh_track_order.argtypes = [ctypes.POINTER(Pixels), ctypes.c_int64, P, P, P, P, P, ctypes.c_size_t, P, P,
                                       P]
     lib.raysh_track_order.restype = I
+    lib.raysh_set_lens.argtypes = [P, ctypes.POINTER(Lens)]
+    lib.raysh_set_lens.restype = I
     lib.raysh_fma_probe.argtypes = [I, ctypes.c_int64, ctypes.c_int32, P, P]
     lib.raysh_fma_probe.restype = I
     F = ctypes.c_float
@@ -202,30 +204,44 @@ def _stream_handle(torch, device, stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _lens_struct(lens):
+    """(raysh_lens, the arrays it points into, n_stars, (kappa_c, gamma1,
+    gamma2)) for a lens given as a tuple (kappa_c, gamma1, gamma2, x, y, m)
+    or an object with as_tuple()."""
+    if hasattr(lens, "as_tuple"):
+        lens = lens.as_tuple()
+    kc, g1, g2, x, y, m = lens
+    arrays = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, m)]
+    n = len(arrays[0])
+    if not (len(arrays[1]) == n and len(arrays[2]) == n):
+        raise ValueError("star arrays differ in length")
+    cl = Lens(float(kc), float(g1), float(g2), n, *(a.ctypes.data if n else None for a in arrays))
+    return cl, arrays, n, (float(kc), float(g1), float(g2))
+
+
 class Context:
     """A lens (kappa_c, gamma, stars) resident on one GPU (raysh_init)."""
 
     def __init__(self, lens, device: int = 0, stream=None):
         torch = _torch()
         lib = load()
-        if hasattr(lens, "as_tuple"):
-            lens = lens.as_tuple()
-        kc, g1, g2, x, y, m = lens
-        self._x = np.ascontiguousarray(x, dtype=np.float64)
-        self._y = np.ascontiguousarray(y, dtype=np.float64)
-        self._m = np.ascontiguousarray(m, dtype=np.float64)
-        n = len(self._x)
-        if not (len(self._y) == n and len(self._m) == n):
-            raise ValueError("star arrays differ in length")
-        cl = Lens(float(kc), float(g1), float(g2), n,
-                  self._x.ctypes.data if n else None, self._y.ctypes.data if n else None,
-                  self._m.ctypes.data if n else None)
+        cl, keep, n, macro = _lens_struct(lens)
         self.device = int(device)
         self._ptr = ctypes.c_void_p()
         check(lib.raysh_init(ctypes.byref(self._ptr), ctypes.byref(cl), self.device,
                              _stream_handle(torch, self.device, stream)))
+        del keep
         self.n_stars = n
-        self.lens = (float(kc), float(g1), float(g2))
+        self.lens = macro
+
+    def set_lens(self, lens):
+        """raysh_set_lens: another lens (kappa_c, gamma, stars) in this
+        context, without creating a new one."""
+        cl, keep, n, macro = _lens_struct(lens)
+        check(load().raysh_set_lens(self.handle, ctypes.byref(cl)))
+        del keep
+        self.n_stars = n
+        self.lens = macro
 
     @property
     def handle(self):

@@ -194,45 +194,53 @@ def generate(n_sets, seed, rays_per_side=4096, npix=512, window=10.0, sigmas_per
     feats, hists, sets = [], [], []
     t_shoot = t_hist = 0.0
     inter = rays = 0
-    for c0 in range(0, len(params), chunk):
-        part = params[c0:c0 + chunk]
-        ctxs, grids = [], []
-        for s, p in enumerate(part):
-            srng = np.random.Generator(np.random.PCG64(seed + star_seed_offset + 1000 + c0 + s))
-            m = W.salpeter_masses(p["n_stars"], srng)
-            x, y, _ = W.star_field(m, p["kappa_star"], srng)
-            ctxs.append(R.Context((p["kappa_c"], p["gamma"], 0.0, x, y, m), device=device))
-            grids.append(W.centred_rays(p["hx"], p["hy"], rays_per_side, rays_per_side))
-            inter += rays_per_side ** 2 * p["n_stars"]
-            rays += rays_per_side ** 2
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        if precision == "fp64_expansion":
-            maps = [c.map(g, pix, precision) for c, g in zip(ctxs, grids)]
-        else:
-            maps = R.map_batch(ctxs, grids, [pix] * len(part), precision)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        t_shoot += t1 - t0
-        sig = sample_sigmas(sig_rng, len(part) * sigmas_per_map).reshape(len(part), sigmas_per_map)
-        out = torch.empty((len(part) * sigmas_per_map, N_BINS), dtype=torch.float32, device="cuda")
-        bins = torch.empty(N_BINS, dtype=torch.int32, device="cuda")
-        for s, p in enumerate(part):
-            g = grids[s]
-            norm = (g.dx * g.dy) / (pix.Px * pix.Py)
-            mu_ref = W.mean_magnification(p["kappa"], p["gamma"], 0.0)
-            for q in range(sigmas_per_map):
-                hist(maps[s], norm, sig[s, q], pix.Px, pix.Py, mu_ref,
-                     out=(bins, out[s * sigmas_per_map + q]))
-                feats.append([p["kappa"], p["gamma"], p["f"], math.log10(sig[s, q])])
-                sets.append(c0 + s)
-        hists.append(out.cpu().numpy())
-        torch.cuda.synchronize()
-        t_hist += time.perf_counter() - t1
-        for c in ctxs:
+    pool = []   # one context per set of a chunk, given each chunk's lenses (raysh_set_lens)
+    try:
+        for c0 in range(0, len(params), chunk):
+            part = params[c0:c0 + chunk]
+            grids = []
+            for s, p in enumerate(part):
+                srng = np.random.Generator(np.random.PCG64(seed + star_seed_offset + 1000 + c0 + s))
+                m = W.salpeter_masses(p["n_stars"], srng)
+                x, y, _ = W.star_field(m, p["kappa_star"], srng)
+                lens = (p["kappa_c"], p["gamma"], 0.0, x, y, m)
+                if s < len(pool):
+                    pool[s].set_lens(lens)
+                else:
+                    pool.append(R.Context(lens, device=device))
+                grids.append(W.centred_rays(p["hx"], p["hy"], rays_per_side, rays_per_side))
+                inter += rays_per_side ** 2 * p["n_stars"]
+                rays += rays_per_side ** 2
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctxs = pool[:len(part)]
+            if precision == "fp64_expansion":
+                maps = [c.map(g, pix, precision) for c, g in zip(ctxs, grids)]
+            else:
+                maps = R.map_batch(ctxs, grids, [pix] * len(part), precision)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            t_shoot += t1 - t0
+            sig = sample_sigmas(sig_rng, len(part) * sigmas_per_map).reshape(len(part), sigmas_per_map)
+            out = torch.empty((len(part) * sigmas_per_map, N_BINS), dtype=torch.float32, device="cuda")
+            bins = torch.empty(N_BINS, dtype=torch.int32, device="cuda")
+            for s, p in enumerate(part):
+                g = grids[s]
+                norm = (g.dx * g.dy) / (pix.Px * pix.Py)
+                mu_ref = W.mean_magnification(p["kappa"], p["gamma"], 0.0)
+                for q in range(sigmas_per_map):
+                    hist(maps[s], norm, sig[s, q], pix.Px, pix.Py, mu_ref,
+                         out=(bins, out[s * sigmas_per_map + q]))
+                    feats.append([p["kappa"], p["gamma"], p["f"], math.log10(sig[s, q])])
+                    sets.append(c0 + s)
+            hists.append(out.cpu().numpy())
+            torch.cuda.synchronize()
+            t_hist += time.perf_counter() - t1
+            if log:
+                log(f"  shot sets {c0}..{c0 + len(part) - 1} ({t_shoot:.1f} s shooting)")
+    finally:
+        for c in pool:
             c.close()
-        if log:
-            log(f"  shot sets {c0}..{c0 + len(part) - 1} ({t_shoot:.1f} s shooting)")
     return Dataset(np.asarray(feats, np.float32), np.concatenate(hists), np.asarray(sets), t_shoot, t_hist,
                    inter, rays)
 

@@ -272,3 +272,8 @@ def test_fma_probe_argument_errors(lib):
     assert lib.raysh_fma_probe(R.FP64, 1, 0, d, None) == R.EINVAL
     assert "n_iter" in _err(lib)
     assert lib.raysh_fma_probe(R.FP64, 1, 1, None, None) == R.EINVAL
+
+
+def test_set_lens_argument_errors(lib):
+    assert lib.raysh_set_lens(None, None) == R.EINVAL
+    assert "ctx" in _err(lib)
