@@ -24,7 +24,10 @@
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, kGemmThreads = 256;
+// BK = 64: the network's products have K of at most a few hundred, so a
+// workgroup's time is its chain of K / BK staging round trips; 64 keeps that
+// chain at four steps for K = 256 (with 16 it was sixteen).
+constexpr int BM = 64, BN = 64, BK = 64, kGemmThreads = 256;
 
 enum Epilogue {
     EPI_STORE = 0,       // C = acc
@@ -166,13 +169,26 @@ __global__ __launch_bounds__(64) void softmax_xent_kernel(const float *__restric
     if (row_loss && threadIdx.x == 0) row_loss[b] = l;
 }
 
-// out[n] = sum_b X[b][n], b in order (one thread per column).
-__global__ void column_sum_kernel(const float *__restrict__ X, int B, int N, float *__restrict__ out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// out[n] = sum_b X[b][n] in a fixed order: a workgroup takes kSumCols
+// columns; thread (column c, group r) sums rows r, r + kSumGroups, ... in
+// order, and the groups' partial sums are then added in order of r.
+constexpr int kSumCols = 16, kSumGroups = 16;
+
+__global__ __launch_bounds__(kSumCols * kSumGroups) void column_sum_kernel(const float *__restrict__ X, int B,
+                                                                           int N, float *__restrict__ out) {
+    __shared__ float part[kSumGroups][kSumCols + 1];
+    const int c = threadIdx.x % kSumCols, r = threadIdx.x / kSumCols;
+    const int n = blockIdx.x * kSumCols + c;
     float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += X[(int64_t)b * N + n];
-    out[n] = s;
+    if (n < N)
+        for (int b = r; b < B; b += kSumGroups) s += X[(int64_t)b * N + n];
+    part[r][c] = s;
+    __syncthreads();
+    if (r == 0 && n < N) {
+        float t = 0.0f;
+        for (int g = 0; g < kSumGroups; ++g) t += part[g][c];
+        out[n] = t;
+    }
 }
 
 // Mean of row losses (one workgroup, fixed order).
@@ -408,17 +424,20 @@ int raysh_mlp_gradient(raysh_mlp *p, const float *x, const float *target, int32_
     float *G = p->grad;
     // layer 3
     gemm<true, false, false, EPI_STORE>(s, p->H2, h, p->dZ3, no, h, no, B, G + p->off[4], no);
-    hipLaunchKernelGGL(column_sum_kernel, dim3((no + 255) / 256), dim3(256), 0, s, p->dZ3, B, no, G + p->off[5]);
+    hipLaunchKernelGGL(column_sum_kernel, dim3((no + kSumCols - 1) / kSumCols), dim3(kSumCols * kSumGroups), 0,
+                       s, p->dZ3, B, no, G + p->off[5]);
     gemm<false, true, true, EPI_GELU_GRAD>(s, p->dZ3, no, p->w16 + p->woff[2], no, B, h, no, p->dZ2, h, nullptr,
                                            p->Z2);
     // layer 2
     gemm<true, false, false, EPI_STORE>(s, p->H1, h, p->dZ2, h, h, h, B, G + p->off[2], h);
-    hipLaunchKernelGGL(column_sum_kernel, dim3((h + 255) / 256), dim3(256), 0, s, p->dZ2, B, h, G + p->off[3]);
+    hipLaunchKernelGGL(column_sum_kernel, dim3((h + kSumCols - 1) / kSumCols), dim3(kSumCols * kSumGroups), 0,
+                       s, p->dZ2, B, h, G + p->off[3]);
     gemm<false, true, true, EPI_GELU_GRAD>(s, p->dZ2, h, p->w16 + p->woff[1], h, B, h, h, p->dZ1, h, nullptr,
                                            p->Z1);
     // layer 1
     gemm<true, false, false, EPI_STORE>(s, x, ni, p->dZ1, h, ni, h, B, G + p->off[0], h);
-    hipLaunchKernelGGL(column_sum_kernel, dim3((h + 255) / 256), dim3(256), 0, s, p->dZ1, B, h, G + p->off[1]);
+    hipLaunchKernelGGL(column_sum_kernel, dim3((h + kSumCols - 1) / kSumCols), dim3(kSumCols * kSumGroups), 0,
+                       s, p->dZ1, B, h, G + p->off[1]);
     if (loss) hipLaunchKernelGGL(mean_loss_kernel, dim3(1), dim3(256), 0, s, p->row_loss, B, loss);
     if (grads) {
         hipError_t e = hipMemcpyAsync(grads, G, p->n_params * sizeof(float), hipMemcpyDeviceToDevice, s);
