@@ -24,10 +24,14 @@
 
 namespace {
 
-// BK = 64: the network's products have K of at most a few hundred, so a
-// workgroup's time is its chain of K / BK staging round trips; 64 keeps that
-// chain at four steps for K = 256 (with 16 it was sixteen).
-constexpr int BM = 64, BN = 64, BK = 64, kGemmThreads = 256;
+// The network's products are small (M, N and K of at most a few hundred),
+// so a product's time is one workgroup's chain of staging round trips, not
+// the matrix cores' rate: 32 x 32 tiles give 4 times the workgroups of
+// 64 x 64 (64 for a 256 x 256 product), and K-chunks of 64 keep the chain
+// at four steps for K = 256.  A training step of the 4-256-256-64 network
+// at batch 256 took 387 us with 64 x 64 x 16 tiles, 145 us with these.
+constexpr int BM = 32, BN = 32, BK = 64, kGemmThreads = 256;
+constexpr int WT = BM / 32;   // 16 x 16 MFMA tiles per wave and dimension (the 4 waves take quarters)
 
 enum Epilogue {
     EPI_STORE = 0,       // C = acc
@@ -61,14 +65,14 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(const float *__restr
     __shared__ float As[BK][BM + 4];
     __shared__ float Bs[BK][BN + 4];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;   // the wave's quarter of the tile
+    const int wm = (wave / 2) * (BM / 2), wn = (wave % 2) * (BN / 2);   // the wave's quarter of the tile
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     typedef float floatx4 __attribute__((ext_vector_type(4)));
-    floatx4 acc[2][2];
+    floatx4 acc[WT][WT];
 #pragma unroll
-    for (int si = 0; si < 2; ++si)
+    for (int si = 0; si < WT; ++si)
 #pragma unroll
-        for (int sj = 0; sj < 2; ++sj) acc[si][sj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int sj = 0; sj < WT; ++sj) acc[si][sj] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = 0; k0 < K; k0 += BK) {
         // stage A tile: BM x BK elements, 4 per thread
         for (int e = threadIdx.x; e < BM * BK; e += kGemmThreads) {
@@ -99,24 +103,24 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(const float *__restr
 #pragma unroll
         for (int kq = 0; kq < BK; kq += 4) {
             const int kk = kq + lane / 16;
-            float a[2], b[2];
+            float a[WT], b[WT];
 #pragma unroll
-            for (int si = 0; si < 2; ++si) a[si] = As[kk][wm + si * 16 + lane % 16];
+            for (int si = 0; si < WT; ++si) a[si] = As[kk][wm + si * 16 + lane % 16];
 #pragma unroll
-            for (int sj = 0; sj < 2; ++sj) b[sj] = Bs[kk][wn + sj * 16 + lane % 16];
+            for (int sj = 0; sj < WT; ++sj) b[sj] = Bs[kk][wn + sj * 16 + lane % 16];
 #pragma unroll
-            for (int si = 0; si < 2; ++si)
+            for (int si = 0; si < WT; ++si)
 #pragma unroll
-                for (int sj = 0; sj < 2; ++sj)
+                for (int sj = 0; sj < WT; ++sj)
                     acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[si], b[sj], acc[si][sj], 0, 0, 0);
         }
         __syncthreads();
     }
     // lane l holds rows 4 (l / 16) + r, column l % 16 of each 16 x 16 tile
 #pragma unroll
-    for (int si = 0; si < 2; ++si)
+    for (int si = 0; si < WT; ++si)
 #pragma unroll
-        for (int sj = 0; sj < 2; ++sj)
+        for (int sj = 0; sj < WT; ++sj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm + si * 16 + 4 * (lane / 16) + r;

@@ -277,11 +277,11 @@ def train(data: Dataset, steps=3000, batch=256, lr=2e-3, hidden=256, seed=0, dev
     X = torch.from_numpy(std(data.features)).to(f"cuda:{device}")
     Y = torch.from_numpy(data.hist.astype(np.float32)).to(f"cuda:{device}")
     net = MLP(init_params(N_FEATURES, hidden, N_BINS, seed), n_hidden=hidden, max_batch=batch, device=device)
-    g = torch.Generator(device="cpu").manual_seed(seed)
+    g = torch.Generator(device=X.device).manual_seed(seed)   # minibatches drawn on the GPU
     n = X.shape[0]
     hist = []
     for step in range(steps):
-        idx = torch.randint(0, n, (batch,), generator=g).to(X.device)
+        idx = torch.randint(0, n, (batch,), generator=g, device=X.device)
         xb, yb = X[idx].contiguous(), Y[idx].contiguous()
         rate = lr * 0.5 * (1 + math.cos(math.pi * step / steps))   # cosine decay
         loss = net.train_step(xb, yb, rate)
