@@ -516,6 +516,8 @@ def main():
     if not args.no_probe:
         print("# FMA probe", file=sys.stderr, flush=True)
         out["fma_probe"] = fma_probe_section(torch, raysh, args.runs, args.no_fp32)
+        # the shooter against the FMA rate this machine sustains at its clock under load
+        out["roofline"]["frac_of_fma_probe"] = achieved / out["fma_probe"]["fp64"]["tflops"]
     if not args.no_fp32:
         print("# fp32_bulk", file=sys.stderr, flush=True)
         c32 = torch.zeros_like(counts)
@@ -549,6 +551,8 @@ def main():
                          "traffic": measured_traffic("plain-fp64-large tile32 %d,%d,%d,%d" % tile32,
                                                      PROFILE_FP32, "shoot_fp32_kernel"),
                          "kernel_ms": k32, "flop_per_launch": FLOP_PER_INTERACTION * inter}}
+        if "fma_probe" in out and "fp32_bulk" in out["fma_probe"]:
+            out["fp32_bulk"]["roofline"]["frac_of_fma_probe"] = ach32 / out["fma_probe"]["fp32_bulk"]["tflops"]
     ctx.close()
     del counts
     # end to end, as the paper times a map: context and star upload, one map,
