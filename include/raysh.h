@@ -132,8 +132,9 @@ int raysh_init(raysh_ctx **out, const raysh_lens *lens, int device, void *hip_st
  * raysh_set_lens: give an existing context another lens (kappa_c, gamma and
  * star field), as raysh_init would, without creating a context: for runs of
  * many maps of different lenses (the grids of simulations of Sec. 1 and
- * Sec. 2.2).  Waits for the work enqueued on the context's stream (it used
- * the old stars), then copies the new stars into the context's device
+ * Sec. 2.2).  Waits for all work on the context's device (work enqueued
+ * before the call may read the old stars, also in a batch led by another
+ * context on another stream), then copies the new stars into its device
  * buffer, growing it when the field is larger (by half again at least),
  * and returns when they are on the device; the caller may then free its
  * arrays.  Captured batch launches that include the context and its star

@@ -381,8 +381,10 @@ int raysh_set_lens(raysh_ctx *ctx, const raysh_lens *lens) {
     const size_t total = (size_t)(n > 0 ? n : 1);   // one zero record when there are no stars
     DeviceGuard g(ctx->device);
     if (!g.ok) return set_error(RAYSH_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
-    // work enqueued before this call reads the old stars
-    hipError_t e = hipStreamSynchronize(ctx->stream);
+    // work enqueued before this call may read the old stars: on the
+    // context's stream, and in a batch led by another context, on its
+    // stream; so the whole device drains first
+    hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_error(e, "raysh_set_lens");
     if ((int64_t)total > ctx->star_capacity) {
         // grow by half again at least, so that a run of growing fields reallocates rarely
