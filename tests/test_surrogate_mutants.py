@@ -53,6 +53,7 @@ def _mutant_module(tmp_path, name):
     return mod
 
 
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")   # a planted mistake may divide by zero
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(tmp_path, name):
     mod = _mutant_module(tmp_path, name)
