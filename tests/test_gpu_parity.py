@@ -347,6 +347,36 @@ def test_batch_with_empty_and_ragged_sets(torch, small_batch):
             c.close()
 
 
+def test_batch_with_starless_and_one_star_sets(torch, small_batch):
+    """Sets of 0, 1 and 2 stars beside a full one in one batch: in both
+    precisions each set's map equals its single-launch map, and the FP64
+    maps of the small sets equal the oracle's (up to rays within the beta
+    bar of a pixel edge)."""
+    w = small_batch[0]
+    lenses = [(0.1, 0.2, 0.0, [], [], []),
+              (0.0, 0.3, -0.1, [0.21], [-0.37], [0.8]),
+              (0.2, -0.1, 0.05, [0.5, -1.1], [0.3, 0.9], [0.4, 1.0]),
+              w.lens.as_tuple()]
+    ctxs = [R.Context(l) for l in lenses]
+    try:
+        rays, pix = [w.rays] * len(lenses), [w.pix] * len(lenses)
+        for prec in ("fp64", "fp32_bulk"):
+            maps = R.map_batch(ctxs, rays, pix, prec)
+            for k, (c, m) in enumerate(zip(ctxs, maps)):
+                np.testing.assert_array_equal(_np(m), _np(c.map(w.rays, w.pix, prec)), err_msg=f"{prec} set {k}")
+        maps = R.map_batch(ctxs, rays, pix, "fp64")
+        threads = max(1, min(16, os.cpu_count() or 1))
+        for k in range(3):
+            ox, oy, ob, sc = _oracle_threaded(lenses[k], w.rays, w.pix.as_tuple(), threads)
+            want = np.bincount(ob[ob >= 0].ravel(), minlength=w.pix.NX * w.pix.NY).reshape(w.pix.NY, w.pix.NX)
+            n_near = int(_near_edges(ox, oy, sc, w.pix.as_tuple()).sum())
+            g = _np(maps[k])
+            _assert_map(g, want, int((ob >= 0).sum()), int(g.sum()), n_near, f"set {k} against the oracle")
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_batch_matches_oracle(torch, small_batch):
     """Every set's batched map against the oracle's map of that set (the
     oracle's per-ray bins on host threads): FP64 equal up to the rays near
