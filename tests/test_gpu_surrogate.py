@@ -116,6 +116,34 @@ def test_mlp_adam_matches_oracle(torch):
     net.close()
 
 
+@pytest.mark.parametrize("n_in,h,n_out,B", [(3, 100, 37, 45), (7, 33, 65, 1), (1, 130, 5, 200), (9, 64, 17, 64)])
+def test_mlp_ragged_sizes_match_oracle(torch, n_in, h, n_out, B):
+    """Layer sizes and batches that are not multiples of the GEMM tiles
+    (32 x 32 outputs, 64 deep) or of the column sums' 16 columns: forward,
+    gradient and one Adam step against the oracle, at the full batch."""
+    rng = np.random.default_rng(n_in * 1000 + h)
+    params = OS.init_params(n_in, h, n_out, rng)
+    params = (params + rng.normal(0, 0.05, params.shape)).astype(np.float32)
+    x = rng.standard_normal((B, n_in)).astype(np.float32)
+    t = rng.random((B, n_out)).astype(np.float32)
+    t /= t.sum(axis=1, keepdims=True)
+    net = S.MLP(params, n_in=n_in, n_hidden=h, n_out=n_out, max_batch=B)
+    try:
+        xg, tg = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+        want, _ = OS.forward(params, x, n_in, h, n_out)
+        np.testing.assert_allclose(net.forward(xg).cpu().numpy(), want, rtol=2e-4, atol=1e-7)
+        g, loss = net.gradient(xg, tg)
+        g = g.cpu().numpy().astype(np.float64)
+        gw = OS.gradients(params, x, t, n_in, h, n_out)
+        assert abs(loss.item() - OS.loss(params, x, t, n_in, h, n_out)) < 1e-5
+        assert np.linalg.norm(g - gw) / np.linalg.norm(gw) < 1e-4
+        net.adam_step(1e-3)
+        p, _, _ = OS.adam(params, g.astype(np.float32), np.zeros_like(params), np.zeros_like(params), 1, 1e-3)
+        np.testing.assert_allclose(net.params(), p, rtol=1e-6, atol=1e-7)
+    finally:
+        net.close()
+
+
 def test_mlp_rejects_bad_batch(torch):
     params, x, _ = _net_case()
     net = S.MLP(params, max_batch=16)
