@@ -445,6 +445,35 @@ def test_star_on_a_ray_drops_only_that_ray(torch, parts):
             _assert_map(_np(m), counts, int((ob >= 0).sum()), nb, int(near.sum()), str(shape))
 
 
+FP32_BETA_TOL = 1e-5   # FP32-bulk: ~30 FP32 terms of relative error < 1e-6 each, partial sums in FP64
+
+
+def test_star_on_a_ray_fp32_bulk(torch):
+    """FP32-bulk with stars exactly on lattice points: only the rays on
+    stars are dropped; every other ray's beta is within 1e-5 S of the
+    oracle's and, away from pixel edges by more than that, in its pixel."""
+    rng = np.random.default_rng(42)
+    lens, rays, on = _on_star_lens(rng)
+    pix = (-2.0, -2.0, 4 / 64, 4 / 64, 64, 64)
+    ox, oy, ob = ora.shoot(lens, rays, pix)
+    s = ora.error_scale_block(lens, rays)
+    fin = np.isfinite(ox) & np.isfinite(oy)
+    assert np.count_nonzero(~fin) == len(on)
+    X0, Y0, Px, Py = pix[:4]
+    with np.errstate(invalid="ignore"):
+        du = np.abs((ox - X0) / Px - np.round((ox - X0) / Px)) * Px
+        dv = np.abs((oy - Y0) / Py - np.round((oy - Y0) / Py)) * Py
+    band = fin & ((du <= FP32_BETA_TOL * s) | (dv <= FP32_BETA_TOL * s))
+    with R.Context(lens) as ctx:
+        for shape in FP32_SHAPES:
+            ctx.set_tile("fp32_bulk", shape[0], shape[1], star_tile=shape[2])
+            gx, gy, gb = (_np(t) for t in ctx.shoot(rays, "fp32_bulk", pix))
+            assert np.array_equal(np.isfinite(gx) & np.isfinite(gy), fin), shape
+            assert np.all(np.abs(gx[fin] - ox[fin]) <= FP32_BETA_TOL * s[fin]), shape
+            assert np.all(np.abs(gy[fin] - oy[fin]) <= FP32_BETA_TOL * s[fin]), shape
+            assert np.count_nonzero((gb != ob) & ~band) == 0, shape
+
+
 def test_star_on_a_ray_in_a_batch(torch):
     """The same lens in a batch, beside another set, for every FP64 shape:
     its batched map equals the oracle's."""
