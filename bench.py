@@ -355,7 +355,7 @@ def surrogate_section(steps):
     """The learned part at its full size: 4096 shooter-generated 512^2 maps
     (4096^2 rays each, FP64 with the far field expanded) over sampled
     (kappa, gamma, kappa_*/kappa), four Gaussian sources per map; the
-    network trained on them by the library's kernels; judged on 256
+    network trained on them by the library's kernels; evaluated on 256
     held-out sets against the mean of four star-field realisations each;
     out-of-domain queries answered by the plain FP64 shooter."""
     from paper_1703_09707_amd import surrogate as S

@@ -7,7 +7,7 @@ parameter sets.  Here the shooter generates maps over sampled
 sizes, gives a 64-bin histogram of log10(mu_sigma / mu_macro); a small network
 (4 -> 256 -> 256 -> 64, BF16 weights, FP32 accumulation) learns to predict
 the histogram from (kappa, gamma, kappa_*/kappa, log10 sigma).  The shooter
-remains the judge: held-out histograms are compared by L1 distance with the
+remains the reference: held-out histograms are compared by L1 distance with the
 network's predictions, with the realisation-noise floor (two star fields at
 the same parameters) and with a no-network baseline (the nearest training
 example in standardised feature space).
@@ -16,7 +16,7 @@ Queries go through ``Surrogate``: a query whose standardised features lie
 inside the training data's box and near a training example is answered by
 the network; any other query is answered by shooting its map and taking its
 histogram (the plain shooter as fallback), so the surrogate never
-extrapolates.  The held-out judge compares with the mean histogram of
+extrapolates.  The held-out evaluation compares with the mean histogram of
 several star-field realisations per parameter set, so that it measures the
 network's error and not the scatter of one realisation.
 
@@ -375,7 +375,7 @@ def evaluate(net, std, train_data: Dataset, test_data: Dataset, noise_data: Data
     test_data holds one star-field realisation per held-out set; the
     `realisations` (more Datasets of the same sets and sources, other star
     fields) join it in the target, which is then the mean histogram of all
-    of them (so the judge measures the network's error rather than the
+    of them (so the evaluation measures the network's error rather than the
     scatter of one realisation).  noise_data, one more independent
     realisation, gives the realisation-noise floor: its L1 to the same
     target."""
@@ -464,7 +464,7 @@ def run(train_sets=4096, test_sets=256, rays=4096, npix=512, sigmas=4, steps=200
         precision="fp64_expansion", seed=W.BASE_SEED + 4, realisations=4, log=None):
     """The whole learned part at a given size: shoot the training maps and
     the held-out maps (`realisations` star fields per held-out set, plus one
-    more for the noise floor), train, judge, time the network against the
+    more for the noise floor), train, evaluate, time the network against the
     shooter and answer out-of-domain queries through the fallback.  Returns
     a dict of results."""
     torch = _torch()
@@ -545,7 +545,7 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp64_expansion",
                     help="how the maps are shot: fp64_expansion, fp32_bulk or fp64")
     ap.add_argument("--realisations", type=int, default=4,
-                    help="star fields per held-out set averaged into the judge's target")
+                    help="star fields per held-out set averaged into the evaluation's target")
     ap.add_argument("--seed", type=int, default=W.BASE_SEED + 4)
     ap.add_argument("--out", default=None, help="write the JSON result here too")
     a = ap.parse_args(argv)
