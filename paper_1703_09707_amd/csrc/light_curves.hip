@@ -286,6 +286,12 @@ constexpr int kCellPx = 16;
 constexpr int kMaxCellsPerSide = 2048;
 constexpr int kScanThreads = 1024;
 
+// Cell counters one 128-byte cache line apart while there are few cells:
+// every track of a cell adds to its counter, and atomics on one line are
+// served one after another (with 4096 cells, 32 counters a line took 256 x
+// 32 atomics each).  Beyond 32768 cells the tracks spread over enough lines.
+inline int counter_stride(int64_t n_keys) { return n_keys <= 32768 ? 32 : 1; }
+
 struct CellGrid {
     double x0, y0, ipx, ipy;   // map origin and inverse pixel size
     int cell_px;               // pixels per cell side
@@ -338,22 +344,22 @@ __global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
 
 __global__ __launch_bounds__(kLcThreads) void track_count_kernel(CellGrid c, const double *xa, const double *ya,
                                                                  const double *xb, const double *yb,
-                                                                 int64_t n_tracks, uint32_t *counts) {
+                                                                 int64_t n_tracks, int stride, uint32_t *counts) {
     const int64_t t = (int64_t)blockIdx.x * kLcThreads + threadIdx.x;
     if (t >= n_tracks) return;
-    atomicAdd(&counts[track_key(c, xa[t], ya[t], xb[t], yb[t])], 1u);
+    atomicAdd(&counts[(int64_t)track_key(c, xa[t], ya[t], xb[t], yb[t]) * stride], 1u);
 }
 
-// Exclusive prefix sum of counts[0, n) in place (one workgroup): each thread
-// sums a contiguous run, the runs' sums are scanned in LDS, then each thread
-// rewrites its run.
-__global__ __launch_bounds__(kScanThreads) void track_scan_kernel(uint32_t *counts, int64_t n) {
+// Exclusive prefix sum of counts[0], counts[stride], ... (n values) in place
+// (one workgroup): each thread sums a contiguous run, the runs' sums are
+// scanned in LDS, then each thread rewrites its run.
+__global__ __launch_bounds__(kScanThreads) void track_scan_kernel(uint32_t *counts, int64_t n, int stride) {
     __shared__ uint32_t part[kScanThreads];
     const int64_t per = (n + kScanThreads - 1) / kScanThreads;
     const int64_t lo = std::min<int64_t>((int64_t)threadIdx.x * per, n);
     const int64_t hi = std::min<int64_t>(lo + per, n);
     uint32_t sum = 0;
-    for (int64_t i = lo; i < hi; ++i) sum += counts[i];
+    for (int64_t i = lo; i < hi; ++i) sum += counts[i * stride];
     part[threadIdx.x] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -367,20 +373,20 @@ __global__ __launch_bounds__(kScanThreads) void track_scan_kernel(uint32_t *coun
     __syncthreads();
     uint32_t run = part[threadIdx.x];
     for (int64_t i = lo; i < hi; ++i) {
-        const uint32_t v = counts[i];
-        counts[i] = run;
+        const uint32_t v = counts[i * stride];
+        counts[i * stride] = run;
         run += v;
     }
 }
 
 __global__ __launch_bounds__(kLcThreads) void track_scatter_kernel(CellGrid c, const double *xa, const double *ya,
                                                                    const double *xb, const double *yb,
-                                                                   int64_t n_tracks, uint32_t *offsets,
+                                                                   int64_t n_tracks, int stride, uint32_t *offsets,
                                                                    int32_t *order, double *sorted) {
     const int64_t t = (int64_t)blockIdx.x * kLcThreads + threadIdx.x;
     if (t >= n_tracks) return;
     const double ax = xa[t], ay = ya[t], bx = xb[t], by = yb[t];
-    const uint32_t pos = atomicAdd(&offsets[track_key(c, ax, ay, bx, by)], 1u);
+    const uint32_t pos = atomicAdd(&offsets[(int64_t)track_key(c, ax, ay, bx, by) * stride], 1u);
     order[pos] = (int32_t)t;   // pos < n_tracks: the offsets partition [0, n_tracks)
     if (sorted) {
         sorted[pos] = ax;
@@ -487,7 +493,8 @@ extern "C" int raysh_source_map(const int32_t *counts, int32_t nx, int32_t ny, d
 extern "C" size_t raysh_track_order_workspace(const raysh_pixels *grid) {
     if (!grid || validate_pixels(grid) != RAYSH_OK) return 0;
     const CellGrid c = cell_grid(grid);
-    return 4 * ((size_t)c.side * (size_t)c.side + 1);
+    const int64_t n_keys = (int64_t)c.side * c.side;
+    return 4 * ((size_t)n_keys * (size_t)counter_stride(n_keys) + 1);
 }
 
 extern "C" int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, const double *xa, const double *ya,
@@ -524,14 +531,16 @@ extern "C" int raysh_track_order(const raysh_pixels *grid, int64_t n_tracks, con
     hipStream_t s = (hipStream_t)hip_stream;
     const CellGrid c = cell_grid(grid);
     const int64_t n_keys = (int64_t)c.side * c.side;
+    const int stride = counter_stride(n_keys);
+    const int64_t n_words = n_keys * stride;
     uint32_t *counts = (uint32_t *)workspace;
     const unsigned tb_blocks = (unsigned)((n_tracks + kLcThreads - 1) / kLcThreads);
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n_keys + 255) / 256)), dim3(256), 0, s, counts, n_keys);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n_words + 255) / 256)), dim3(256), 0, s, counts, n_words);
     hipLaunchKernelGGL(track_count_kernel, dim3(tb_blocks), dim3(kLcThreads), 0, s, c, xa, ya, xb, yb, n_tracks,
-                       counts);
-    hipLaunchKernelGGL(track_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, n_keys);
+                       stride, counts);
+    hipLaunchKernelGGL(track_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, n_keys, stride);
     hipLaunchKernelGGL(track_scatter_kernel, dim3(tb_blocks), dim3(kLcThreads), 0, s, c, xa, ya, xb, yb, n_tracks,
-                       counts, order, sorted);
+                       stride, counts, order, sorted);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "raysh_track_order");
     return set_ok();

@@ -249,8 +249,13 @@ def test_source_map_and_light_curve_argument_errors(lib):
     to = lib.raysh_track_order
     assert lib.raysh_track_order_workspace(None) == 0
     assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 0, 16))) == 0
-    # 1012 pixels a side: 64 cells of 16 pixels, Morton keys over 64 x 64
-    assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 1012, 1012))) == 4 * (64 * 64 + 1)
+    # 1012 pixels a side: 64 cells of 16 pixels, Morton keys over 64 x 64,
+    # their counters a 128-byte line (32 words) apart
+    assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 1012, 1012))) == \
+        4 * (64 * 64 * 32 + 1)
+    # 2896 pixels a side: 181 cells, keys over 256 x 256 (65536 > 32768): counters packed
+    assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 2896, 2896))) == \
+        4 * (256 * 256 + 1)
     # 40000 pixels a side: cells grow to 32 pixels (1250 a side), keys over 2048 x 2048
     assert lib.raysh_track_order_workspace(ctypes.byref(R.Pixels(0.0, 0.0, 0.1, 0.1, 40000, 100))) == \
         4 * (2048 * 2048 + 1)
