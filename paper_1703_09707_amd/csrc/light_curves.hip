@@ -352,26 +352,26 @@ __global__ __launch_bounds__(kLcThreads) void track_count_kernel(CellGrid c, con
 
 // Exclusive prefix sum of counts[0], counts[stride], ... (n values) in place
 // (one workgroup): each thread sums a contiguous run, the runs' sums are
-// scanned in LDS, then each thread rewrites its run.
+// scanned (within each wave by shuffles, then the waves' totals in turn),
+// then each thread rewrites its run.
 __global__ __launch_bounds__(kScanThreads) void track_scan_kernel(uint32_t *counts, int64_t n, int stride) {
-    __shared__ uint32_t part[kScanThreads];
+    __shared__ uint32_t wave_tot[kScanThreads / 64];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int64_t per = (n + kScanThreads - 1) / kScanThreads;
     const int64_t lo = std::min<int64_t>((int64_t)threadIdx.x * per, n);
     const int64_t hi = std::min<int64_t>(lo + per, n);
     uint32_t sum = 0;
     for (int64_t i = lo; i < hi; ++i) sum += counts[i * stride];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int i = 0; i < kScanThreads; ++i) {
-            const uint32_t v = part[i];
-            part[i] = run;
-            run += v;
-        }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t up = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += up;
     }
+    if (lane == 63) wave_tot[wave] = incl;
     __syncthreads();
-    uint32_t run = part[threadIdx.x];
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w) run += wave_tot[w];
     for (int64_t i = lo; i < hi; ++i) {
         const uint32_t v = counts[i * stride];
         counts[i * stride] = run;

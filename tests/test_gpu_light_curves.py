@@ -210,6 +210,53 @@ def test_track_order(torch, small_map):
             assert torch.equal(torch.nan_to_num(plain, nan=-1.0), torch.nan_to_num(ordered, nan=-1.0))
 
 
+def _cell_keys(grid, tracks):
+    """Each track's sort key as the header states it: the Morton number of
+    the 16 x 16-pixel cell (cells doubled while more than 2048 a side)
+    holding the midpoint of its end points, midpoints outside the map
+    clamped to the nearest edge cell."""
+    x0, y0, px, py, nx, ny = grid
+    cell = 16
+    while (max(nx, ny) + cell - 1) // cell > 2048:
+        cell *= 2
+    cx_n, cy_n = (nx + cell - 1) // cell, (ny + cell - 1) // cell
+    mx, my = 0.5 * (tracks[0] + tracks[2]), 0.5 * (tracks[1] + tracks[3])
+
+    def cells(m, o, ip, n):
+        c = ((m - o) * ip) / float(cell)
+        with np.errstate(invalid="ignore"):
+            k = np.where(c >= 0.0, np.minimum(c, n - 1), 0.0)
+        return np.where(np.isnan(c), 0, np.floor(k)).astype(np.int64)
+
+    cx, cy = cells(mx, x0, 1.0 / px, cx_n), cells(my, y0, 1.0 / py, cy_n)
+    key = np.zeros(len(mx), np.int64)
+    for b in range(12):
+        key |= ((cx >> b) & 1) << (2 * b) | ((cy >> b) & 1) << (2 * b + 1)
+    return key
+
+
+@pytest.mark.parametrize("side", [1012, 4096])
+def test_track_order_sorted_by_cell(torch, side):
+    """The order visits cells in Morton order, every track in its
+    midpoint's cell, for a map of 64 x 64 cells (counters a cache line
+    apart) and one of 256 x 256 (counters packed); tracks beyond the map
+    edges go to the edge cells."""
+    grid = (-5.0, -4.0, 10.0 / side, 8.0 / side, side, side)
+    rng = np.random.default_rng(side)
+    n = 300_000
+    mid_x, mid_y = rng.uniform(-5.5, 5.5, n), rng.uniform(-4.5, 4.5, n)   # some midpoints off the map
+    ang, half = rng.uniform(0, 2 * np.pi, n), rng.uniform(0.0, 0.5, n)
+    tracks = [mid_x - half * np.cos(ang), mid_y - half * np.sin(ang),
+              mid_x + half * np.cos(ang), mid_y + half * np.sin(ang)]
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in tracks]
+    order, srt = R.track_order(grid, *dev, sorted_end_points=True)
+    o = order.cpu().numpy()
+    assert np.array_equal(np.sort(o), np.arange(n))
+    keys = _cell_keys(grid, tracks)[o]
+    assert np.all(np.diff(keys) >= 0)
+    assert np.array_equal(srt.cpu().numpy(), np.stack([a[o] for a in tracks]))
+
+
 def test_track_order_entries_outside_are_skipped(torch, small_map):
     w, counts, _, norm = small_map
     mu, grid = R.source_map(counts, w.pix, norm, "disk", 2.0 * w.pix.Px)
