@@ -98,9 +98,13 @@ def test_golden_exact_tiny(torch):
                 np.testing.assert_array_equal(counts, np.array(g["counts"]))
 
 
-@pytest.mark.parametrize("kc,g1,g2", [(0.25, 0.125, 0.0625), (0.5, -0.25, 0.1875)])
+@pytest.mark.parametrize("kc,g1,g2", [(0.25, 0.125, 0.0625), (0.5, -0.25, 0.1875),
+                                      (1.0, 0.0, 0.0), (0.75, 0.25, 0.0)])
 def test_dyadic_sheet_exact(torch, kc, g1, g2):
-    """No stars: every beta and pixel is exact, so GPU equals oracle bit for bit."""
+    """No stars: every beta and pixel is exact, so GPU equals oracle bit for
+    bit.  The last two sheets are critical (det A = 0): kappa = 1 sends every
+    ray to beta = 0, a pixel corner of the window, and kappa + gamma1 = 1
+    sends every ray to beta_x = 0, a column edge."""
     lens = (kc, g1, g2, [], [], [])
     rays = (-2.0 - 1 / 64, -1.5 - 1 / 128, 1 / 32, 1 / 64, 128, 192, 0, 0)
     pix = (-1.5, -1.25, 1 / 16, 1 / 8, 48, 20)

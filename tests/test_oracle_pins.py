@@ -89,7 +89,8 @@ def test_off_centre_star_translation(oracle_lib):
 
 # ----------------------------------------------------------------- sheets
 @pytest.mark.parametrize("kc,g1,g2", [(0.25, 0.125, 0.0), (0.25, 0.125, 0.0625),
-                                      (0.5, -0.25, 0.1875), (0.0, 0.0, 0.0)])
+                                      (0.5, -0.25, 0.1875), (0.0, 0.0, 0.0),
+                                      (1.0, 0.0, 0.0), (0.75, 0.25, 0.0)])
 def test_dyadic_sheet_is_exact(oracle_lib, kc, g1, g2):
     """No stars and dyadic kappa_c, gamma, lattice and window: every beta and
     pixel coordinate is exact in FP64, so the oracle equals exact rational
@@ -107,6 +108,26 @@ def test_dyadic_sheet_is_exact(oracle_lib, kc, g1, g2):
         assert b[j, i] == p
         ties += edge == 0
     assert ties > 0  # the lattice puts some rays exactly on pixel edges
+
+
+def test_critical_sheets_collapse(oracle_lib):
+    """det A = 0 (Eq. (3) with no stars): kappa_c = 1, gamma = 0 sends every
+    ray to beta = 0, and kappa_c + gamma1 = 1, gamma2 = 0 sends every ray to
+    beta_x = 0 with beta_y = (1 - kappa_c + gamma1) theta_y.  With beta = 0 on
+    a pixel corner of the window, the half-open pixels put every ray in the
+    pixel above and to the right of it."""
+    rays = (-2.0 - 1 / 64, -1.5 - 1 / 128, 1 / 32, 1 / 64, 128, 192, 0, 0)
+    pix = (-1.5, -1.25, 1 / 16, 1 / 8, 48, 20)
+    corner = 10 * 48 + 24   # row (0 + 1.25) / (1/8), column (0 + 1.5) / (1/16)
+    bx, by, b = oracle_lib.shoot((1.0, 0.0, 0.0, [], [], []), rays, pix)
+    assert np.all(bx == 0.0) and np.all(by == 0.0) and np.all(b == corner)
+    counts, n = oracle_lib.map_counts((1.0, 0.0, 0.0, [], [], []), rays, pix)
+    assert n == 128 * 192 and counts.ravel()[corner] == n
+    bx, by, b = oracle_lib.shoot((0.75, 0.25, 0.0, [], [], []), rays, pix)
+    ty = -1.5 + np.arange(192) / 64
+    assert np.all(bx == 0.0) and np.all(by == 0.5 * ty[:, None])
+    inside = (0.5 * ty >= -1.25) & (0.5 * ty < -1.25 + 20 / 8)
+    assert np.all(b[inside] % 48 == 24) and np.all(b[~inside] == -1)
 
 
 def test_sheet_area_law(oracle_lib):
