@@ -1005,3 +1005,44 @@ def test_large_config_full_band_every_ray(torch):
         frac = np.count_nonzero(_np(fb) != ob) / ob.size
         _say("fp32_bulk misbinned fraction against the oracle", frac)
         assert frac <= MISBIN_FP32
+
+
+@pytest.mark.skipif(os.environ.get("RAYSH_FULL_LATTICE") != "1",
+                    reason="about 4 minutes of oracle time on 16 host threads (the error scale takes a square "
+                           "root and a division per interaction); run with RAYSH_FULL_LATTICE=1")
+def test_large_config_whole_lattice_every_ray(torch):
+    """Every ray of the 8192^2 lattice of the large configuration (6.7e7
+    rays x 16384 stars, 1.1e12 interactions) against the oracle, band by
+    band on the host's cores: one-pass FP64 and the expansion mode in the
+    oracle's pixel (beta within 1e-12 S) away from pixel edges, FP32-bulk
+    at most 1e-4 misbinned, and the FP64 map of the whole lattice (the
+    launch the benchmark times) equal to the histogram of the oracle's bins
+    up to the edge-band rays."""
+    w = W.plain_fp64_large()
+    pix = w.pix.as_tuple()
+    threads = max(1, min(16, os.cpu_count() or 1))
+    band_rows = 512
+    want = np.zeros(w.pix.NX * w.pix.NY, np.int64)
+    n_near = n32 = 0
+    with R.Context(w.lens) as ctx:
+        for j0 in range(0, w.rays.ny, band_rows):
+            band = w.rays.block(0, j0, w.rays.nx, min(band_rows, w.rays.ny - j0))
+            ox, oy, ob, sc = _oracle_threaded(w.lens.as_tuple(), band, pix, threads)
+            near = _near_edges(ox, oy, sc, pix)
+            n_near += int(near.sum())
+            want += np.bincount(ob[ob >= 0].ravel(), minlength=want.size)
+            worst = 0.0
+            for prec in ("fp64", "fp64_expansion"):
+                gx, gy, gb = (_np(t) for t in ctx.shoot(band, prec, w.pix))
+                d = np.maximum(np.abs(gx - ox), np.abs(gy - oy)) / sc
+                worst = max(worst, float(np.max(d)))
+                assert np.all(d <= BETA_TOL), (prec, j0)
+                _assert_bins(gb, ob, near, f"{prec} rows {j0}..")
+            _, _, fb = ctx.shoot(band, "fp32_bulk", w.pix, beta=False)
+            n32 += np.count_nonzero(_np(fb) != ob)
+            _say(f"rows {j0}..{j0 + band.ny - 1}: max |dbeta|/S {worst:.2e}, near edges {int(near.sum())}")
+        frac = n32 / (w.rays.nx * w.rays.ny)
+        _say("fp32_bulk misbinned fraction against the oracle", frac)
+        assert frac <= MISBIN_FP32
+        m, nb = ctx.map(w.rays, w.pix, "fp64", n_binned=True)
+        _assert_map(_np(m).ravel(), want, int(want.sum()), nb, n_near, "whole-lattice FP64 map")
