@@ -403,32 +403,63 @@ __global__ __launch_bounds__(kThreads, 2) void partial_fp64_kernel(ShootParams p
     }
 }
 
-// Finish of split-K: alpha = K theta, then the parts' partial sums in part
-// order, then beta, pixel and counts as in one pass.
+// Split-K, second step: for every ray, alpha = K theta, then the parts'
+// partial sums added in part order; the total overwrites part 0's slot.
+// One thread per ray, so that every compute unit takes part (a lattice of
+// few rays is few tiles), with the loads of kSumAhead parts issued before
+// their additions.
+constexpr int kSumAhead = 8;
+
+__global__ __launch_bounds__(kThreads) void sum_parts_kernel(ShootParams p, int parts,
+                                                             double2 *__restrict__ partial) {
+    const int64_t n_rays = p.nx * p.ny;
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n_rays) return;
+    const int64_t j = r / p.nx, i = r - j * p.nx;
+    double ax, ay;
+    macro_term(p, image_angle(p.x0, p.i0 + i, p.dx), image_angle(p.y0, p.j0 + j, p.dy), ax, ay);
+    int q = 0;
+    for (; q + kSumAhead <= parts; q += kSumAhead) {
+        double2 v[kSumAhead];
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) v[u] = partial[(int64_t)(q + u) * n_rays + r];
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) {
+            ax += v[u].x;
+            ay += v[u].y;
+        }
+    }
+    for (; q < parts; ++q) {
+        const double2 v = partial[(int64_t)q * n_rays + r];
+        ax += v.x;
+        ay += v.y;
+    }
+    partial[r] = make_double2(ax, ay);
+}
+
+// Split-K, last step: each ray's alpha from sum_parts_kernel, then beta,
+// pixel and counts as in one pass.
 template <int CX, int CY>
-__global__ __launch_bounds__(kThreads) void finish_fp64_kernel(ShootParams p, int parts,
-                                                               const double2 *__restrict__ partial) {
+__global__ __launch_bounds__(kThreads) void finish_fp64_kernel(ShootParams p, const double2 *__restrict__ alpha) {
     __shared__ BinShared sh;
     bin_shared_init(sh);
     double tx[CX], ty[CY];
     int64_t tile_i, tile_j;
     int lx, ly;
     tile_rays<CX, CY>(p, blockIdx.x, tx, ty, tile_i, tile_j, lx, ly);
-    const int64_t n_rays = p.nx * p.ny;
     double ax[CY][CX], ay[CY][CX];
 #pragma unroll
     for (int b = 0; b < CY; ++b) {
 #pragma unroll
         for (int a = 0; a < CX; ++a) {
-            macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
             const int64_t i = tile_i + lx + kLanesX * a;
             const int64_t j = tile_j + ly + kLanesY * b;
             if (i < p.nx && j < p.ny) {
-                for (int q = 0; q < parts; ++q) {
-                    const double2 v = partial[q * n_rays + j * p.nx + i];
-                    ax[b][a] += v.x;
-                    ay[b][a] += v.y;
-                }
+                const double2 v = alpha[j * p.nx + i];
+                ax[b][a] = v.x;
+                ay[b][a] = v.y;
+            } else {
+                macro_term(p, tx[a], ty[b], ax[b][a], ay[b][a]);
             }
         }
     }
@@ -482,7 +513,12 @@ hipError_t launch_split(const ShootParams &p, int parts, double2 *partial, hipSt
                        0, s, q, n_tiles, chunk, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((finish_fp64_kernel<CX, CY>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, q, parts,
+    const int64_t n_rays = q.nx * q.ny;
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n_rays + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       q, parts, (double2 *)partial);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((finish_fp64_kernel<CX, CY>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, q,
                        (const double2 *)partial);
     return hipGetLastError();
 }
