@@ -558,6 +558,7 @@ def main():
     # end to end, as the paper times a map: context and star upload, one map,
     # the map back on the host (into a pinned buffer the caller keeps)
     host_map = torch.empty((w.pix.NY, w.pix.NX), dtype=torch.int32, pin_memory=True)
+    host_map.copy_(torch.zeros((w.pix.NY, w.pix.NX), dtype=torch.int32, device="cuda"))   # its first use
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx = raysh.Context(w.lens, device=0)
